@@ -1,0 +1,210 @@
+"""CPU oracle for the micro-edge path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps ``mer_oracle.c`` (plain C, built with gcc,
+no code shared with the GPU library) and walks a multi-view scene one view at
+a time, in float64 unless a discrete outcome is decided (see the C file).
+
+Functions follow the paper's modules (supplement, "Implementation detail"):
+rasterisation -> index image, barycentrics/depth at the index image,
+interpolation and its adjoint (the smooth term Omega), and the EdgeGrad
+backward (Sec. 4.2-4.4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mer_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+NO_INTERSECT = 1
+PAIRS_H_ONLY = 2   # test aid: horizontal neighbour pairs only
+PAIRS_V_ONLY = 4   # test aid: vertical neighbour pairs only
+
+
+def build() -> str:
+    """Compile the oracle with gcc (no fused multiply-add, IEEE semantics)."""
+    tmp = _LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+           "-shared", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i, i64 = ctypes.c_int, ctypes.c_int64
+        L.orc_rasterize.argtypes = [P, i, P, i, i, i, i, P, P]
+        L.orc_rasterize.restype = i
+        L.orc_raster_sample.argtypes = [P, i, P, i, i, P, P, P]
+        L.orc_cover_count.argtypes = [P, i, P, i, i, i, P]
+        L.orc_cover_query.argtypes = [P, i, P, i, i, i]
+        L.orc_cover_query.restype = i
+        L.orc_resolve.argtypes = [P, i, P, i, i, P, P, P, P]
+        L.orc_interpolate.argtypes = [P, i, P, i, P, i, i, P, i, P]
+        L.orc_interpolate_bwd.argtypes = [P, i, P, i, P, i, i, P, i, P, P, P]
+        L.orc_edge_grad.argtypes = [P, i, P, i, i, P, P, P, i, i, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------- one view
+def rasterize(v, tri, H, W, brute=False, with_key=False):
+    v, tri = _f32(v), _i32(tri)
+    tid = np.empty(H * W, np.int32)
+    key = np.empty(H * W, np.float32) if with_key else None
+    culled = lib().orc_rasterize(_p(v), v.shape[0], _p(tri), tri.shape[0], H, W, int(brute), _p(tid), _p(key))
+    return (tid, key, culled) if with_key else tid
+
+
+def raster_sample(v, tri, px, py):
+    v, tri, px, py = _f32(v), _i32(tri), _i32(px), _i32(py)
+    out = np.empty(px.shape[0], np.int32)
+    lib().orc_raster_sample(_p(v), v.shape[0], _p(tri), tri.shape[0], px.shape[0], _p(px), _p(py), _p(out))
+    return out
+
+
+def cover_count(v, tri, H, W):
+    v, tri = _f32(v), _i32(tri)
+    out = np.empty(H * W, np.int32)
+    lib().orc_cover_count(_p(v), v.shape[0], _p(tri), tri.shape[0], H, W, _p(out))
+    return out
+
+
+def cover_query(v, tri, t, px, py):
+    v, tri = _f32(v), _i32(tri)
+    return bool(lib().orc_cover_query(_p(v), v.shape[0], _p(tri), int(t), int(px), int(py)))
+
+
+def resolve(v, tri, H, W, tri_id):
+    v, tri, tri_id = _f32(v), _i32(tri), _i32(tri_id)
+    depth = np.empty(H * W)
+    bary = np.empty((H * W, 3))
+    beta = np.empty((H * W, 3))
+    lib().orc_resolve(_p(v), v.shape[0], _p(tri), H, W, _p(tri_id), _p(depth), _p(bary), _p(beta))
+    return depth, bary, beta
+
+
+def interpolate(attr, v, tri, H, W, tri_id, append_z=False):
+    attr, v, tri, tri_id = _f32(attr), _f32(v), _i32(tri), _i32(tri_id)
+    C_a = attr.shape[1]
+    out = np.empty((H * W, C_a + int(append_z)))
+    lib().orc_interpolate(_p(attr), C_a, _p(v), v.shape[0], _p(tri), H, W, _p(tri_id), int(append_z), _p(out))
+    return out
+
+
+def interpolate_bwd(attr, v, tri, H, W, tri_id, g_out, append_z=False, g_attr=None, g_v=None):
+    attr, v, tri, tri_id, g_out = _f32(attr), _f32(v), _i32(tri), _i32(tri_id), _f64(g_out)
+    C_a = attr.shape[1]
+    if g_attr is None:
+        g_attr = np.zeros((v.shape[0], C_a))
+    if g_v is None:
+        g_v = np.zeros((v.shape[0], 3))
+    assert g_attr.dtype == np.float64 and g_attr.flags.c_contiguous
+    assert g_v.dtype == np.float64 and g_v.flags.c_contiguous
+    lib().orc_interpolate_bwd(_p(attr), C_a, _p(v), v.shape[0], _p(tri), H, W, _p(tri_id), int(append_z),
+                              _p(g_out), _p(g_attr), _p(g_v))
+    return g_attr, g_v
+
+
+def edge_grad(v, tri, H, W, tri_id, img, g, flags=0, g_v=None, want_frag=False, counts=None):
+    v, tri, tri_id, img, g = _f32(v), _i32(tri), _i32(tri_id), _f64(img), _f64(g)
+    C = img.shape[1]
+    assert g.shape == img.shape
+    if g_v is None:
+        g_v = np.zeros((v.shape[0], 3))
+    frag = np.zeros((H * W, 3)) if want_frag else None
+    if counts is None:
+        counts = np.zeros(4, np.int64)
+    lib().orc_edge_grad(_p(v), v.shape[0], _p(tri), H, W, _p(tri_id), _p(img), _p(g), C, int(flags),
+                        _p(g_v), _p(frag), _p(counts))
+    return (g_v, frag) if want_frag else g_v
+
+
+# ------------------------------------------------------- whole scene (views)
+def _view_slices(scene, i):
+    vw = scene.view(i)
+    vs = scene.v[vw["v_off"]: vw["v_off"] + vw["n_v"]]
+    ts = scene.tri[vw["t_off"]: vw["t_off"] + vw["n_t"]]
+    ats = scene.attr[vw["a_off"]: vw["a_off"] + vw["n_v"]]
+    return vw, vs, ts, ats
+
+
+def forward(scene, views=None):
+    """Per-pixel outputs over all views, packed like the GPU buffers.
+
+    Returns dict: tri_id i32 [n_px], depth f64 [n_px], bary f64 [n_px,3],
+    interp f64 [n_px, C_out], image f64 [n_px, C_e] (interp + optional mask).
+    """
+    n_px = scene.n_px
+    out = dict(tri_id=np.full(n_px, -1, np.int32), depth=np.zeros(n_px), bary=np.zeros((n_px, 3)),
+               interp=np.zeros((n_px, scene.C_out)), image=np.zeros((n_px, scene.C_e)))
+    for i in (range(scene.n_views) if views is None else views):
+        vw, vs, ts, ats = _view_slices(scene, i)
+        H, W, o = vw["H"], vw["W"], vw["px_off"]
+        tid = rasterize(vs, ts, H, W)
+        d, b, _ = resolve(vs, ts, H, W, tid)
+        it = interpolate(ats, vs, ts, H, W, tid, scene.append_z)
+        sl = slice(o, o + H * W)
+        out["tri_id"][sl] = tid
+        out["depth"][sl] = d
+        out["bary"][sl] = b
+        out["interp"][sl] = it
+        out["image"][sl, :scene.C_out] = it
+        if scene.mask_channel:
+            out["image"][sl, scene.C_out] = (tid >= 0).astype(np.float64)
+    return out
+
+
+def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None):
+    """Fused backward over all views: g_v [sum V_view, 3], g_attr [sum V_attr, C_a].
+
+    ``g_img`` is dL/d(image) [n_px, C_e]; its first C_out channels are also
+    dL/d(interpolated attributes).
+    """
+    g_img = np.asarray(g_img, np.float64)
+    g_v = np.zeros((scene.v.shape[0], 3))
+    g_attr = np.zeros((scene.attr.shape[0], scene.C_a))
+    for i in (range(scene.n_views) if views is None else views):
+        vw, vs, ts, ats = _view_slices(scene, i)
+        H, W, o = vw["H"], vw["W"], vw["px_off"]
+        sl = slice(o, o + H * W)
+        gv = np.zeros((vw["n_v"], 3))
+        ga = np.zeros((vw["n_v"], scene.C_a))
+        tid = fwd["tri_id"][sl]
+        if edge:
+            edge_grad(vs, ts, H, W, tid, fwd["image"][sl], g_img[sl], flags=flags, g_v=gv)
+        if interp:
+            interpolate_bwd(ats, vs, ts, H, W, tid, np.ascontiguousarray(g_img[sl, :scene.C_out]),
+                            scene.append_z, g_attr=ga, g_v=gv)
+        g_v[vw["v_off"]: vw["v_off"] + vw["n_v"]] += gv
+        g_attr[vw["a_off"]: vw["a_off"] + vw["n_v"]] += ga
+    return g_v, g_attr
