@@ -1,0 +1,286 @@
+"""Benchmark: forward + backward Mpixels/s of the micro-edge path on one GPU.
+
+A step is one pass of the whole path over one batch of views, with the
+inputs resident in HBM: rasterize (set-up, binning, tiled z-buffer, resolve),
+interpolate, the L2 image loss gradient g = 2 (I - T) (torch), clearing the
+gradient buffers, and the fused micro-edge + interpolation backward.
+Batched = all views of the workload in one captured HIP graph; per-view =
+the same calls issued view by view without a graph.
+
+Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build measures
+one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
+
+WORKLOADS = {
+    4: "batched: 256 displaced-icosphere scenes (1k-200k tris, 10% intersecting pairs), 128-1024 px square",
+    2: "one 512x512 view of two interpenetrating displaced icospheres (nu=64, 163,840 tris)",
+    3: "head-like mesh (60,500 tris), 64 views at 1024x667",
+    5: "2M-tri intersecting pair, 16 views at 2048x2048, barycentrics recomputed",
+    1: "icosphere nu=4 (320 tris), one 64x64 view",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Step:
+    """Device buffers and the call sequence of one step for a set of views."""
+
+    def __init__(self, scene, groups, tile, store_bary, dev):
+        import torch
+
+        from paper_2405_02508_amd import mer
+        s = scene
+        self.s = s
+        self.dev = dev
+        self.v = torch.from_numpy(s.v).to(dev)
+        self.tri = torch.from_numpy(s.tri).to(dev)
+        self.attr = torch.from_numpy(s.attr).to(dev)
+        n = s.n_px
+        self.tid = torch.empty(n, dtype=torch.int32, device=dev)
+        self.depth = torch.empty(n, dtype=torch.float32, device=dev)
+        self.bary = torch.empty(n, 2, dtype=torch.float32, device=dev) if store_bary else None
+        self.img = torch.empty(n, s.C_e, dtype=torch.float32, device=dev)
+        self.interp = self.img if s.C_e == s.C_out else torch.empty(n, s.C_out, dtype=torch.float32, device=dev)
+        self.g = torch.empty(n, s.C_e, dtype=torch.float32, device=dev)
+        self.g_v = torch.zeros_like(self.v)
+        self.g_attr = torch.zeros_like(self.attr)
+        self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile) for grp in groups]
+        # L2 target image rendered once from perturbed vertices (outside the timed region)
+        self.target = torch.zeros(n, s.C_e, dtype=torch.float32, device=dev)
+        if s.v_target is not None:
+            vt = torch.from_numpy(s.v_target).to(dev)
+            for c in self.ctxs:
+                c.rasterize(vt, self.tri, self.tid, None, self.bary)
+                c.interpolate(self.attr, vt, self.tri, self.tid, self.interp, bary=self.bary, append_z=s.append_z)
+            self._assemble()
+            self.target.copy_(self.img)
+        else:
+            self.target.copy_(torch.rand(n, s.C_e, generator=torch.Generator(device=dev).manual_seed(7), device=dev))
+
+    def _assemble(self):
+        if self.img is not self.interp:
+            self.img[:, : self.s.C_out].copy_(self.interp)
+            self.img[:, self.s.C_out].copy_((self.tid >= 0).float())
+
+    def forward(self):
+        s = self.s
+        for c in self.ctxs:
+            c.rasterize(self.v, self.tri, self.tid, self.depth, self.bary)
+        for c in self.ctxs:
+            c.interpolate(self.attr, self.v, self.tri, self.tid, self.interp, bary=self.bary, append_z=s.append_z)
+        self._assemble()
+
+    def loss_grad(self):
+        import torch
+        torch.sub(self.img, self.target, out=self.g)
+        self.g.mul_(2.0)
+
+    def backward(self):
+        self.g_v.zero_()
+        self.g_attr.zero_()
+        for c in self.ctxs:
+            c.backward(self.v, self.tri, self.tid, self.attr, self.img, self.g, self.g_attr, self.g_v,
+                       append_z=self.s.append_z)
+
+    def run(self):
+        self.forward()
+        self.loss_grad()
+        self.backward()
+
+
+def time_region(fn, steps, stream):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def kernel_times(st, iters, stream):
+    """Average duration of each library call on its stream, HIP events."""
+    import torch
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    names = ("rasterize", "interpolate", "backward")
+    acc = {k: 0.0 for k in names}
+    for _ in range(iters):
+        marks = [ev() for _ in range(4)]
+        marks[0].record(stream)
+        for c in st.ctxs:
+            c.rasterize(st.v, st.tri, st.tid, st.depth, st.bary)
+        marks[1].record(stream)
+        for c in st.ctxs:
+            c.interpolate(st.attr, st.v, st.tri, st.tid, st.interp, bary=st.bary, append_z=st.s.append_z)
+        st._assemble()
+        st.loss_grad()
+        st.g_v.zero_()
+        st.g_attr.zero_()
+        marks[2].record(stream)
+        for c in st.ctxs:
+            c.backward(st.v, st.tri, st.tid, st.attr, st.img, st.g, st.g_attr, st.g_v, append_z=st.s.append_z)
+        marks[3].record(stream)
+        torch.cuda.synchronize()
+        acc["rasterize"] += marks[0].elapsed_time(marks[1])
+        acc["interpolate"] += marks[1].elapsed_time(marks[2])
+        acc["backward"] += marks[2].elapsed_time(marks[3])
+    return {k: acc[k] / iters for k in names}
+
+
+def algorithmic_bytes(s, kernel):
+    """Bytes the method must move per launch (model stated in the design notes)."""
+    n_px = s.n_px
+    V = s.views
+    view_tris = int(V[:, 5].sum())
+    view_verts = int(V[:, 4].sum())
+    if kernel == "backward":
+        # read tri_id, image, dL/dimage per pixel; per view-triangle its index row,
+        # per view-vertex its position and gradient row (read + write)
+        return n_px * (4 + 8 * s.C_e) + view_tris * 12 + view_verts * 12 * 3 + s.attr.size * 4 * 3
+    if kernel == "rasterize":
+        # per view-triangle index row, per view-vertex position; write tri_id, depth (+bary)
+        return view_tris * 12 + view_verts * 12 + n_px * (8 + (8 if not s.recompute else 0))
+    if kernel == "interpolate":
+        return n_px * (4 + (8 if not s.recompute else 0) + 4 * s.C_out) + s.attr.size * 4 + view_tris * 12
+    raise KeyError(kernel)
+
+
+def cpu_baseline(scene, budget_s=15.0):
+    """The CPU oracle as it stands (single thread) on a bounded sample of the
+    workload: whole views, forward + backward, until the time budget is used."""
+    import oracle
+    oracle.lib()
+    n_views, px = 0, 0
+    t0 = time.perf_counter()
+    for i in range(scene.n_views):
+        px += oracle.step_view(scene, i)
+        n_views += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(px / dt / 1e6, 4), "unit": "Mpx/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_views} of {scene.n_views} views ({px} px), forward+backward, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=4, choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default="8x8")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-per-view", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2405_02508_amd import mer, scenes
+    mer.lib()  # fail loudly if the HIP library is missing
+    dev = torch.device("cuda:0")
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    t0 = time.perf_counter()
+    s = scenes.make_config(args.workload)
+    log(f"[bench] workload {args.workload} {s.name}: {s.n_views} views, {s.n_px} px, "
+        f"{int(s.views[:, 5].sum())} view-tris, scene built in {time.perf_counter() - t0:.1f}s")
+    stream = torch.cuda.current_stream()
+
+    # ---- batched: every view in one plan, captured in a HIP graph
+    st = Step(s, [list(range(s.n_views))], tile, not s.recompute, dev)
+    for _ in range(args.warmup):
+        st.run()
+    torch.cuda.synchronize()
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(stream)
+        with torch.cuda.stream(cs):
+            st.run()
+            torch.cuda.synchronize()
+            with torch.cuda.graph(graph, stream=cs):
+                st.run()
+        stream.wait_stream(cs)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        run_batched = graph.replay
+    else:
+        run_batched = st.run
+    ms = time_region(run_batched, args.steps, stream)
+    log(f"[bench] batched {'graph' if graph else 'eager'}: {ms:.3f} ms/step")
+    kt = kernel_times(st, max(3, min(args.steps, 10)), stream)
+    log(f"[bench] per-call ms: {kt}")
+    status = st.ctxs[0].status()
+    log(f"[bench] status {status}")
+
+    # ---- per-view: one plan and one launch sequence per view, no graph
+    pv = None
+    used_graph = graph is not None
+    if not args.no_per_view and s.n_views > 1:
+        graph = None
+        st_pv = Step(s, [[i] for i in range(s.n_views)], tile, not s.recompute, dev)
+        for _ in range(max(1, args.warmup)):
+            st_pv.run()
+        ms_pv = time_region(st_pv.run, max(2, args.steps // 4), stream)
+        pv = {"ms_per_step": round(ms_pv, 4), "value": round(s.n_px / ms_pv / 1e3, 2)}
+        log(f"[bench] per-view eager: {ms_pv:.3f} ms/step")
+        del st_pv
+
+    dom = max(kt, key=kt.get)
+    ab = algorithmic_bytes(s, dom)
+    achieved = ab / (kt[dom] * 1e-3) / 1e9
+    out = {
+        "metric": "fwd+bwd Mpixels/s (raster+micro-edge grad), batched vs per-view, err<=1e-5",
+        "value": round(s.n_px / ms / 1e3, 2),
+        "unit": "Mpx/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"config {args.workload}: {WORKLOADS[args.workload]}", "scene": s.name,
+                   "views": s.n_views, "pixels": s.n_px, "view_triangles": int(s.views[:, 5].sum()),
+                   "tile": args.tile, "graph": used_graph, "barycentrics": "recomputed" if s.recompute else "stored"},
+        "per_view": pv,
+        "per_call_ms": {k: round(v, 4) for k, v in kt.items()},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "algorithmic_bytes": ab},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        del st
+        torch.cuda.empty_cache()
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * mer.h -- C ABI of the micro-edge rasterize / interpolate / edge-gradient
+ * library for AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the module boundaries of the method (supplement,
+ * "Implementation detail"): a rasterizer that writes an index image (visible
+ * triangle per pixel) and a depth image, a barycentrics stage, an attribute
+ * interpolator with its backward pass, and the EdgeGrad backward pass that
+ * turns dL/d(image) into dL/d(vertex position) through micro-edges between
+ * neighbouring pixels (Sec. 4.2 Pixel Pairs, Eq. chain_new; Sec. 4.3 Edge
+ * Classification and Gradient Scattering; Sec. 4.4 Geometry Intersections,
+ * Eq. grad_int).  The EdgeGrad forward pass is the identity and has no call.
+ *
+ * Conventions (all calls):
+ *   - Every data pointer is DEVICE memory owned by the caller.  The library
+ *     allocates nothing and frees nothing.  Scratch memory is the caller's
+ *     workspace, sized by mer_plan_init.
+ *   - Every call enqueues work on `stream` (a hipStream_t; NULL = the null
+ *     stream) and returns without waiting, except mer_status which waits.
+ *     No call allocates or synchronises, so sequences of calls can be
+ *     captured into a HIP graph.
+ *   - Return value: MER_OK (0) or a negative MER_E* code from the synchronous
+ *     argument checks; on error nothing is enqueued.
+ *   - Screen vertices v: float [sum n_v, 3] rows (x_px, y_px, z) -- pixel
+ *     coordinates with y down and the origin at the image corner, z the
+ *     camera depth along the principal axis (> 0 in front of the camera).
+ *     Pixel (x, y) covers [x, x+1) x [y, y+1); its centre is (x+1/2, y+1/2).
+ *   - Triangles tri: int32 [sum n_t, 3] of view-local vertex indices.
+ *   - Per-pixel buffers are packed over views (view i starts at px_off) and
+ *     row-major inside a view (index px_off + y * W + x), channels last.
+ *   - Index image tri_id: int32, view-local triangle index, -1 = background.
+ *   - Gradient outputs (g_v, g_attr) are ACCUMULATED (+=); the caller clears
+ *     them.  Float atomics make the last bits order-dependent.
+ */
+#ifndef MER_H
+#define MER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MER_OK 0
+#define MER_EINVAL (-1)     /* null required pointer, bad size or bad view   */
+#define MER_EWORKSPACE (-2) /* workspace pointer null / plan inconsistent    */
+#define MER_ELAUNCH (-3)    /* a kernel launch failed (hipGetLastError)      */
+#define MER_ETUNING (-4)    /* unsupported tile shape                        */
+
+/* edge-gradient flags */
+#define MER_NO_INTERSECT 1  /* ablation: intersection pairs scatter nothing   */
+#define MER_SKIP_EDGE 2     /* fused backward: skip the micro-edge term       */
+#define MER_SKIP_INTERP 4   /* fused backward: skip the interpolation adjoint */
+
+/* One rasterization job: one view of one mesh.  Views may share triangles
+ * (t_off) and attributes (a_off); each view has its own screen vertices. */
+typedef struct mer_view {
+  int64_t v_off;  /* first row of this view's vertices in v[]                */
+  int64_t t_off;  /* first row of this view's triangles in tri[]             */
+  int64_t a_off;  /* first row of this view's vertex attributes in attr[]   */
+  int64_t px_off; /* first pixel of this view in the per-pixel buffers       */
+  int32_t n_v, n_t, H, W;
+} mer_view;       /* 48 bytes, no padding */
+
+/* Tile shape (pixels) and bin pool capacity (triangle-tile entries; 0 picks
+ * a default from the triangle and tile counts). */
+typedef struct mer_tuning {
+  int32_t tile_w, tile_h; /* supported: 8x8, 16x16, 32x8, 16x8 */
+  int64_t bin_cap;
+} mer_tuning;
+
+/* Host-side plan: totals over the view table and the workspace layout.
+ * Filled by mer_plan_init; treat as opaque apart from ws_bytes. */
+typedef struct mer_plan {
+  int32_t n_views, tile_w, tile_h, pad0;
+  int64_t total_tris, total_tiles, total_px, bin_cap;
+  int64_t px_begin; /* first pixel of the first view (pixel kernels cover [px_begin, total_px)) */
+  int64_t ws_bytes;
+  int64_t off_viewtab, off_rec, off_bbox, off_count, off_offs, off_part, off_bins, off_status;
+  int64_t n_part;
+} mer_plan;
+
+/* Validate the host copy of the view table (H, W in [1, 32767], n_v, n_t >= 0,
+ * offsets >= 0) and fill *plan.  tun may be NULL (8x8 tiles, default pool).
+ * Reads host memory only.  MER_EINVAL on a bad view, MER_ETUNING on an
+ * unsupported tile shape. */
+int mer_plan_init(const mer_view *views_host, int n_views, const mer_tuning *tun, mer_plan *plan);
+
+/* Rasterization module + barycentrics (supplement, "Rasterization module",
+ * "Barycentrics module"; the z-buffer of the Rasterization module).
+ * For every pixel centre: the visible triangle is the one with the largest
+ * interpolated 1/z among triangles whose interior contains the centre
+ * (vertices snapped to 1/256 px; exact integer edge functions; top-left rule
+ * on edges; equal binary32 1/z -> smaller triangle id).  Triangles with an
+ * index outside [0, n_v), a non-finite coordinate, z <= 1e-3 or |x|, |y| >
+ * 2^20 px are culled (counted in mer_status).
+ *   views_dev: device copy of the same view table given to mer_plan_init.
+ *   tri_id: int32 [total_px] out.  depth: float [total_px] out, 1/(1/z) of
+ *   the visible surface, 0 on background; NULL to skip.  bary: float
+ *   [total_px, 2] out, perspective-correct (b0, b1) for tri[t][0], tri[t][1]
+ *   (b2 = 1 - b0 - b1), (0, 0) on background; NULL to skip.
+ *   ws: device workspace of plan->ws_bytes bytes. */
+int mer_rasterize(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                  int32_t *tri_id, float *depth, float *bary, void *ws, void *stream);
+
+/* Interpolation module (supplement, "Interpolation module"):
+ * out[p, c] = sum_k b_k attr[a_off + tri[t][k], c] for c < C_a and, if
+ * append_z, out[p, C_a] = sum_k b_k z_k (screen z of the view's vertices);
+ * 0 on background.  bary may be NULL: the barycentrics are then recomputed
+ * from tri_id and v exactly as mer_rasterize computes them.
+ *   attr: float [*, C_a] (1 <= C_a <= 64).  out: float [total_px, C_a+append_z]. */
+int mer_interpolate(const mer_plan *plan, const mer_view *views_dev, const float *attr, int C_a,
+                    const float *v, const int32_t *tri, const int32_t *tri_id, const float *bary,
+                    int append_z, float *out, void *stream);
+
+/* EdgeGrad backward (Sec. 4.2-4.4): for every horizontal and vertical pair of
+ * neighbouring pixels inside a view whose triangle ids differ,
+ *   dL/dp = 1/2 sum_c (g[A,c] + g[B,c]) (img[A,c] - img[B,c])
+ * with p increasing from A (left/upper) to B.  Pairs are classified by
+ * testing each pixel centre against the other pixel's triangle (same rule as
+ * the rasterizer): one side background -> overhang, neither contained ->
+ * adjacent (nothing), one contained -> overhang with the containing side's
+ * pixel on top, both -> intersection.  Overhang: the top fragment's axis
+ * coordinate gets dL/dp.  Intersection: with s_A, s_B the slopes of the two
+ * triangles' planes in (axis, 1/z), d = s_B - s_A (pair skipped unless
+ * d > 0), u = dL/dp / d: fragment A gets (-s_A u, +u), fragment B
+ * (+s_B u, -u) on (axis, 1/z).  Fragment gradients go to the three vertices
+ * of the pixel's triangle with its screen-space barycentrics at the pixel
+ * centre; the 1/z part reaches z through d(1/z)/dz = -1/z^2.
+ *   img, g_img: float [total_px, C_e] (1 <= C_e <= 64).  g_v: float
+ *   [sum n_v, 3], accumulated.  flags: MER_NO_INTERSECT. */
+int mer_edge_grad(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                  const int32_t *tri_id, const float *img, const float *g_img, int C_e, int flags,
+                  float *g_v, void *stream);
+
+/* Backward of mer_interpolate (supplement: "straightforward differentiation
+ * of the forward pass"), the smooth term Omega of Sec. 3:
+ *   g_attr[a_off + tri[t][k], c] += b_k g_out[p, c]
+ *   g_v (x, y, z) += the derivative through the perspective-correct
+ *   barycentrics (screen barycentrics E_k/D of snapped vertices, snapping
+ *   taken as the identity) and, if append_z, through the z channel.
+ *   g_out: float [total_px, ld_out] with the C_a (+append_z) channels first.
+ *   g_attr: float [*, C_a] accumulated, may be NULL; g_v may be NULL. */
+int mer_interpolate_bwd(const mer_plan *plan, const mer_view *views_dev, const float *attr, int C_a,
+                        const float *v, const int32_t *tri, const int32_t *tri_id, int append_z,
+                        const float *g_out, int ld_out, float *g_attr, float *g_v, void *stream);
+
+/* Both backward passes in one sweep over the pixels: the EdgeGrad term on
+ * (img, g_img, C_e) and the interpolation adjoint on the first C_a+append_z
+ * channels of g_img (so the interpolated attributes must be the first
+ * channels of the image).  flags: MER_NO_INTERSECT, MER_SKIP_EDGE,
+ * MER_SKIP_INTERP. */
+int mer_backward_fused(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                       const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
+                       const float *g_img, int C_e, int flags, float *g_attr, float *g_v, void *stream);
+
+/* Wait for `stream`, then read the workspace status of the last
+ * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool
+ * (they were rasterized by the slower fallback, results unchanged),
+ * out[1] culled triangles, out[2] triangle-tile entries needed, out[3]
+ * bin pool capacity. */
+int mer_status(const mer_plan *plan, const void *ws, void *stream, int64_t out[4]);
+
+const char *mer_strerror(int code);
+int mer_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MER_H */

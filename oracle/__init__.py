@@ -208,3 +208,24 @@ def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None):
         g_v[vw["v_off"]: vw["v_off"] + vw["n_v"]] += gv
         g_attr[vw["a_off"]: vw["a_off"] + vw["n_v"]] += ga
     return g_v, g_attr
+
+
+def step_view(scene, i, target_value=0.5):
+    """Forward + backward of one view with view-local buffers (for timing):
+    rasterize, resolve, interpolate, L2 gradient against a constant target,
+    edge term and interpolation adjoint.  Returns the view's pixel count."""
+    vw, vs, ts, ats = _view_slices(scene, i)
+    H, W = vw["H"], vw["W"]
+    tid = rasterize(vs, ts, H, W)
+    resolve(vs, ts, H, W, tid)
+    it = interpolate(ats, vs, ts, H, W, tid, scene.append_z)
+    img = it
+    if scene.mask_channel:
+        img = np.concatenate([it, (tid >= 0).astype(np.float64)[:, None]], 1)
+    g = 2.0 * (img - target_value)
+    gv = np.zeros((vw["n_v"], 3))
+    ga = np.zeros((vw["n_v"], scene.C_a))
+    edge_grad(vs, ts, H, W, tid, img, g, g_v=gv)
+    interpolate_bwd(ats, vs, ts, H, W, tid, np.ascontiguousarray(g[:, :scene.C_out]), scene.append_z,
+                    g_attr=ga, g_v=gv)
+    return H * W

@@ -1,0 +1,150 @@
+// mer_api.hip -- the C ABI (include/mer.h): plan, argument checks, launches,
+// status.  No call allocates device memory or synchronises (mer_status aside).
+#include <limits.h>
+#include <string.h>
+
+#include "mer_internal.h"
+
+namespace {
+
+constexpr int kVersion = 1;
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+bool tile_supported(int w, int h) {
+  return (w == 8 && h == 8) || (w == 16 && h == 16) || (w == 32 && h == 8) || (w == 16 && h == 8);
+}
+
+}  // namespace
+
+extern "C" {
+
+int mer_version(void) { return kVersion; }
+
+const char* mer_strerror(int code) {
+  switch (code) {
+    case MER_OK: return "ok";
+    case MER_EINVAL: return "invalid argument";
+    case MER_EWORKSPACE: return "workspace missing or inconsistent with the plan";
+    case MER_ELAUNCH: return "kernel launch failed";
+    case MER_ETUNING: return "unsupported tile shape";
+    default: return "unknown error";
+  }
+}
+
+int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer_plan* P) {
+  if (!views || !P || n_views < 1) return MER_EINVAL;
+  const int tw = tun ? tun->tile_w : 8, th = tun ? tun->tile_h : 8;
+  if (!tile_supported(tw, th)) return MER_ETUNING;
+  memset(P, 0, sizeof(*P));
+  int64_t tris = 0, tiles = 0, px_end = 0;
+  for (int i = 0; i < n_views; ++i) {
+    const mer_view& w = views[i];
+    if (w.H < 1 || w.W < 1 || w.H > 32767 || w.W > 32767) return MER_EINVAL;
+    if (w.n_v < 0 || w.n_t < 0 || w.v_off < 0 || w.t_off < 0 || w.a_off < 0 || w.px_off < 0) return MER_EINVAL;
+    if (w.px_off < px_end) return MER_EINVAL;  // views packed in order, no overlap
+    px_end = w.px_off + (int64_t)w.H * w.W;
+    tris += w.n_t;
+    tiles += (int64_t)((w.W + tw - 1) / tw) * ((w.H + th - 1) / th);
+  }
+  if (tris > INT_MAX) return MER_EINVAL;
+  P->n_views = n_views;
+  P->tile_w = tw;
+  P->tile_h = th;
+  P->total_tris = tris;
+  P->total_tiles = tiles;
+  P->total_px = px_end;
+  P->px_begin = views[0].px_off;
+  int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 4 * tris + 16 * tiles + 4096;
+  if (cap > INT_MAX) cap = INT_MAX;
+  P->bin_cap = cap;
+  P->n_part = (tiles + 1023) / 1024;
+  int64_t off = 0;
+  P->off_viewtab = off;
+  off = align256(off + 2 * (int64_t)(n_views + 1) * 8);
+  P->off_rec = off;
+  off = align256(off + tris * 64);
+  P->off_bbox = off;
+  off = align256(off + tris * 8);
+  P->off_count = off;
+  off = align256(off + tiles * 4);
+  P->off_offs = off;
+  off = align256(off + (tiles + 1) * 4);
+  P->off_part = off;
+  off = align256(off + P->n_part * 4);
+  P->off_bins = off;
+  off = align256(off + cap * 4);
+  P->off_status = off;
+  off = align256(off + 8 * 8);
+  P->ws_bytes = off;
+  return MER_OK;
+}
+
+static bool plan_ok(const mer_plan* P) {
+  return P && P->n_views >= 1 && P->ws_bytes > 0 && tile_supported(P->tile_w, P->tile_h);
+}
+
+int mer_rasterize(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri, int32_t* tri_id,
+                  float* depth, float* bary, void* ws, void* stream) {
+  if (!plan_ok(P) || !views_dev || !tri_id || (P->total_tris > 0 && (!v || !tri))) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  return mer::launch_rasterize(P, views_dev, v, tri, tri_id, depth, bary, ws, (hipStream_t)stream);
+}
+
+int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,
+                    const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
+                    void* stream) {
+  if (!plan_ok(P) || !views_dev || !attr || !tri || !tri_id || !out || C_a < 1 || C_a > 64) return MER_EINVAL;
+  if ((append_z || !bary) && !v) return MER_EINVAL;
+  return mer::launch_interpolate(P, views_dev, attr, C_a, v, tri, tri_id, bary, append_z ? 1 : 0, out,
+                                 (hipStream_t)stream);
+}
+
+int mer_edge_grad(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                  const int32_t* tri_id, const float* img, const float* g_img, int C_e, int flags, float* g_v,
+                  void* stream) {
+  if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !img || !g_img || !g_v || C_e < 1 || C_e > 64)
+    return MER_EINVAL;
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, nullptr, 0, 0, img, g_img, C_e, C_e,
+                              (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, (hipStream_t)stream);
+}
+
+int mer_interpolate_bwd(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,
+                        const int32_t* tri, const int32_t* tri_id, int append_z, const float* g_out, int ld_out,
+                        float* g_attr, float* g_v, void* stream) {
+  const int C = C_a + (append_z ? 1 : 0);
+  if (!plan_ok(P) || !views_dev || !attr || !v || !tri || !tri_id || !g_out || C_a < 1 || C_a > 64 || ld_out < C)
+    return MER_EINVAL;
+  if (!g_attr && !g_v) return MER_OK;
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, nullptr, g_out, ld_out,
+                              ld_out, MER_SKIP_EDGE, g_attr, g_v, (hipStream_t)stream);
+}
+
+int mer_backward_fused(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                       const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
+                       const float* g_img, int C_e, int flags, float* g_attr, float* g_v, void* stream) {
+  const int C = C_a + (append_z ? 1 : 0);
+  if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !g_img || C_e < 1 || C_e > 64) return MER_EINVAL;
+  if (!(flags & MER_SKIP_EDGE) && (!img || !g_v)) return MER_EINVAL;
+  if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, g_img, C_e, C_e,
+                              flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr, g_v,
+                              (hipStream_t)stream);
+}
+
+int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) {
+  if (!plan_ok(P) || !out) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  long long st[8];
+  if (hipMemcpyAsync(st, (const char*)ws + P->off_status, sizeof(st), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
+      hipSuccess)
+    return MER_ELAUNCH;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MER_ELAUNCH;
+  out[0] = st[0];
+  out[1] = st[1];
+  out[2] = st[2];
+  out[3] = P->bin_cap;
+  return MER_OK;
+}
+
+}  // extern "C"

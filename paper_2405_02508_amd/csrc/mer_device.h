@@ -1,0 +1,221 @@
+// mer_device.h -- device-side pieces shared by the raster and backward kernels.
+//
+// Triangle set-up follows the rasterizer's contract (mer.h): vertices snapped
+// to 1/256 px, exact integer edge functions, top-left rule on edges, depth key
+// = interpolated 1/z in binary32 with a fixed operation order (the library is
+// built with -ffp-contract=off, so nothing below is fused).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mer.h"
+
+namespace mer {
+
+constexpr float kGuard = 1048576.0f;  // |x|,|y| beyond 2^20 px -> culled
+constexpr float kZNear = 1.0e-3f;     // z at or below -> culled
+
+// Per (view, triangle) set-up record, 64 bytes.  For edge k (opposite vertex
+// k) and pixel (px, py):  E'_k = A[k] * (256 px) + B[k] * (256 py) + C[k]
+// equals sign(D) * orient(v_{k+1}, v_{k+2}, centre) + tl_k, so the centre is
+// covered iff all three E'_k > 0; e_k = E'_k - tl_k is the exact value.
+struct __align__(16) Rec {
+  long long C[3];
+  int A[3];
+  int B[3];
+  float q[3];  // 1/z of the three vertices, binary32
+  int tl;      // bit k: edge k is a top or left edge
+};
+static_assert(sizeof(Rec) == 64, "record layout");
+
+// Snapped triangle in fixed point plus 1/z; ok == false when culled.
+struct Snap {
+  int X[3], Y[3];
+  float q[3];
+  float z[3];
+  long long D;  // twice the signed area, fixed point squared
+  int idx[3];
+  bool ok;
+};
+
+__device__ __forceinline__ Snap snap_triangle(const float* __restrict__ v, const mer_view& vw,
+                                              const int32_t* __restrict__ tri_row) {
+  Snap s;
+  s.ok = false;
+  s.D = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int i = tri_row[k];
+    s.idx[k] = i;
+    s.X[k] = s.Y[k] = 0;
+    s.q[k] = s.z[k] = 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int i = s.idx[k];
+    if (i < 0 || i >= vw.n_v) return s;
+    const float* p = v + (vw.v_off + (long long)i) * 3;
+    float x = p[0], y = p[1], z = p[2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return s;
+    if (!(z > kZNear)) return s;
+    if (fabsf(x) > kGuard || fabsf(y) > kGuard) return s;
+    s.X[k] = (int)rintf(x * 256.0f);
+    s.Y[k] = (int)rintf(y * 256.0f);
+    s.q[k] = 1.0f / z;
+    s.z[k] = z;
+  }
+  s.D = (long long)(s.X[1] - s.X[0]) * (long long)(s.Y[2] - s.Y[0]) -
+        (long long)(s.X[2] - s.X[0]) * (long long)(s.Y[1] - s.Y[0]);
+  s.ok = s.D != 0;
+  return s;
+}
+
+// Build the coverage record from a snapped triangle.
+__device__ __forceinline__ Rec make_rec(const Snap& s) {
+  Rec r;
+  const long long sg = s.D > 0 ? 1 : -1;
+  r.tl = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    // orient(va, vb, P) = A * Px + B * Py + C0 with P in fixed point
+    const long long A = -(long long)(s.Y[b] - s.Y[a]);
+    const long long B = (long long)(s.X[b] - s.X[a]);
+    const long long C0 = (long long)(s.Y[b] - s.Y[a]) * s.X[a] - (long long)(s.X[b] - s.X[a]) * s.Y[a];
+    const long long As = sg * A, Bs = sg * B;
+    // inward normal (As, Bs): left edge iff As > 0, top edge iff As == 0 && Bs > 0
+    const int tl = (As > 0 || (As == 0 && Bs > 0)) ? 1 : 0;
+    r.A[k] = (int)As;
+    r.B[k] = (int)Bs;
+    r.C[k] = sg * (C0 + 128 * A + 128 * B) + tl;
+    r.tl |= tl << k;
+    r.q[k] = s.q[k];
+  }
+  return r;
+}
+
+// Biased edge functions at pixel (px, py).
+__device__ __forceinline__ void edge_eval(const Rec& r, int px, int py, long long E[3]) {
+  const long long PX = (long long)px * 256, PY = (long long)py * 256;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) E[k] = (long long)r.A[k] * PX + (long long)r.B[k] * PY + r.C[k];
+}
+
+__device__ __forceinline__ bool covered(const long long E[3]) { return E[0] > 0 && E[1] > 0 && E[2] > 0; }
+
+// Exact unbiased edge values as binary32, and d = (float)(|D|).
+__device__ __forceinline__ void edge_values(const Rec& r, const long long E[3], float e[3], float& d) {
+  long long u0 = E[0] - (r.tl & 1), u1 = E[1] - ((r.tl >> 1) & 1), u2 = E[2] - ((r.tl >> 2) & 1);
+  e[0] = (float)u0;
+  e[1] = (float)u1;
+  e[2] = (float)u2;
+  d = (float)(u0 + u1 + u2);
+}
+
+// Depth key: ((e0 q0 + e1 q1) + e2 q2) / d, one rounding per operation.
+__device__ __forceinline__ float depth_key(const Rec& r, const float e[3], float d) {
+  float a = e[0] * r.q[0];
+  float b = e[1] * r.q[1];
+  float c = e[2] * r.q[2];
+  float n = a + b;
+  n = n + c;
+  return n / d;
+}
+
+// 64-bit visibility key: larger 1/z wins, then smaller triangle id.  1/z > 0,
+// so its IEEE bits order like the value.
+__device__ __forceinline__ unsigned long long vis_key(float q, int t) {
+  return ((unsigned long long)__float_as_uint(q) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)t);
+}
+__device__ __forceinline__ int key_tri(unsigned long long k) {
+  return k == 0ull ? -1 : (int)(0xFFFFFFFFu - (unsigned)(k & 0xFFFFFFFFull));
+}
+__device__ __forceinline__ float key_q(unsigned long long k) { return __uint_as_float((unsigned)(k >> 32)); }
+
+// Is pixel (px, py)'s centre inside snapped triangle s by the coverage rule?
+__device__ __forceinline__ bool contains(const Snap& s, int px, int py) {
+  if (!s.ok) return false;
+  Rec r = make_rec(s);
+  long long E[3];
+  edge_eval(r, px, py, E);
+  return covered(E);
+}
+
+// Screen barycentrics (exact edge values / D), perspective-correct b, W = sum e_k q_k / d.
+struct PixBary {
+  float beta[3];
+  float b[3];
+  float Wq;  // interpolated 1/z
+};
+
+__device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
+  Rec r = make_rec(s);
+  long long E[3];
+  edge_eval(r, px, py, E);
+  float e[3], d;
+  edge_values(r, E, e, d);
+  PixBary o;
+  float w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    o.beta[k] = e[k] / d;
+    w[k] = o.beta[k] * s.q[k];
+  }
+  float W = (w[0] + w[1]) + w[2];
+  o.b[0] = w[0] / W;
+  o.b[1] = w[1] / W;
+  o.b[2] = (1.0f - o.b[0]) - o.b[1];
+  o.Wq = W;
+  return o;
+}
+
+// Slope of the plane through (x_k, y_k, 1/z_k) along axis 0 (x) or 1 (y),
+// binary32 from the snapped vertices, fixed order.
+__device__ __forceinline__ float plane_slope(const Snap& s, int axis) {
+  float dq1 = s.q[1] - s.q[0];
+  float dq2 = s.q[2] - s.q[0];
+  float num;
+  if (axis == 0) {
+    float a = dq1 * (float)((long long)s.Y[2] - s.Y[0]);
+    float b = dq2 * (float)((long long)s.Y[1] - s.Y[0]);
+    num = a - b;
+  } else {
+    float a = dq2 * (float)((long long)s.X[1] - s.X[0]);
+    float b = dq1 * (float)((long long)s.X[2] - s.X[0]);
+    num = a - b;
+  }
+  float n256 = num * 256.0f;
+  return n256 / (float)s.D;
+}
+
+// Largest i in [0, n) with base[i] <= g (base non-decreasing, base[0] <= g).
+template <typename T>
+__device__ __forceinline__ int find_bucket(const T* base, int n, long long g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if ((long long)base[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_view_px(const mer_view* views, int n, long long p) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (views[mid].px_off <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// View of the wave's first pixel, searched with a wave-uniform index so the
+// loads go through the scalar cache.
+__device__ __forceinline__ int wave_view(const mer_view* views, int n, long long p0) {
+  const long long u = ((long long)__builtin_amdgcn_readfirstlane((int)(p0 >> 32)) << 32) |
+                      (unsigned)__builtin_amdgcn_readfirstlane((int)(p0 & 0xffffffff));
+  return __builtin_amdgcn_readfirstlane(find_view_px(views, n, u));
+}
+
+}  // namespace mer

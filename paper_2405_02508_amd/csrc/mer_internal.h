@@ -1,0 +1,16 @@
+// mer_internal.h -- launchers shared between the C-ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "mer_device.h"
+
+namespace mer {
+int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, int32_t* tri_id,
+                     float* depth, float* bary, void* ws, hipStream_t st);
+int launch_interpolate(const mer_plan* P, const mer_view* views, const float* attr, int C_a, const float* v,
+                       const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
+                       hipStream_t st);
+int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
+                    const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
+                    const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, hipStream_t st);
+}  // namespace mer

@@ -1,0 +1,353 @@
+// mer_raster.hip -- triangle set-up, tile binning and the tiled z-buffer
+// rasterizer with barycentric/depth resolve (supplement, "Rasterization
+// module" and "Barycentrics module").
+//
+// Pipeline for one mer_rasterize call over all views:
+//   k_prep      per-view prefix tables (triangles, tiles), clear tile counters
+//   k_setup     one thread per (view, triangle): snap, cull, 64-byte coverage
+//               record, pixel-centre bounding box, count overlapped tiles
+//   k_scan_*    exclusive scan of tile counts -> bin offsets
+//   k_fill      one thread per (view, triangle): write its record index into
+//               every overlapped tile's list
+//   k_raster    one workgroup per tile, one lane per pixel: stage the tile's
+//               records in LDS, exact coverage, binary32 depth key, 64-bit
+//               (1/z, ~id) max; then resolve depth and barycentrics
+#include "mer_internal.h"
+
+namespace mer {
+
+// ----------------------------------------------------------------- prep
+// Block-wide exclusive scan over n values (any n); one block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_prep(const mer_view* __restrict__ views, int n_views, int tw_log2,
+                                               int th_log2, long long* __restrict__ tri_base,
+                                               long long* __restrict__ tile_base, long long* __restrict__ status) {
+  __shared__ long long s_tri[1024], s_tile[1024];
+  const int tid = threadIdx.x;
+  const int per = (n_views + 1023) / 1024;
+  const int lo = tid * per, hi = min(n_views, lo + per);
+  long long a = 0, b = 0;
+  for (int i = lo; i < hi; ++i) {
+    const mer_view vw = views[i];
+    a += vw.n_t;
+    b += (long long)((vw.W + (1 << tw_log2) - 1) >> tw_log2) * ((vw.H + (1 << th_log2) - 1) >> th_log2);
+  }
+  s_tri[tid] = a;
+  s_tile[tid] = b;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    long long x = tid >= off ? s_tri[tid - off] : 0, y = tid >= off ? s_tile[tid - off] : 0;
+    __syncthreads();
+    s_tri[tid] += x;
+    s_tile[tid] += y;
+    __syncthreads();
+  }
+  long long ea = s_tri[tid] - a, eb = s_tile[tid] - b;  // exclusive prefix of this thread's chunk
+  for (int i = lo; i < hi; ++i) {
+    const mer_view vw = views[i];
+    tri_base[i] = ea;
+    tile_base[i] = eb;
+    ea += vw.n_t;
+    eb += (long long)((vw.W + (1 << tw_log2) - 1) >> tw_log2) * ((vw.H + (1 << th_log2) - 1) >> th_log2);
+  }
+  if (tid == 1023) {
+    tri_base[n_views] = s_tri[1023];
+    tile_base[n_views] = s_tile[1023];
+  }
+  if (tid < 8) status[tid] = 0;
+}
+
+__global__ void k_zero_i32(int* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// ---------------------------------------------------------------- setup
+struct BBox {
+  short x0, y0, x1, y1;  // inclusive pixel range; x0 > x1 when empty/culled
+};
+
+__global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ views, int n_views,
+                                               const float* __restrict__ v, const int32_t* __restrict__ tri,
+                                               const long long* __restrict__ tri_base,
+                                               const long long* __restrict__ tile_base, long long total_tris,
+                                               int tw_log2, int th_log2, Rec* __restrict__ rec,
+                                               BBox* __restrict__ bbox, int* __restrict__ count,
+                                               long long* __restrict__ status) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  bool culled = false;
+  if (g < total_tris) {
+    const int vi = find_bucket(tri_base, n_views, g);
+    const mer_view vw = views[vi];
+    const long long t = g - tri_base[vi];
+    const Snap s = snap_triangle(v, vw, tri + (vw.t_off + t) * 3);
+    BBox bb = {1, 1, 0, 0};
+    if (!s.ok) {
+      culled = true;
+    } else {
+      rec[g] = make_rec(s);
+      int xmin = min(s.X[0], min(s.X[1], s.X[2])), xmax = max(s.X[0], max(s.X[1], s.X[2]));
+      int ymin = min(s.Y[0], min(s.Y[1], s.Y[2])), ymax = max(s.Y[0], max(s.Y[1], s.Y[2]));
+      // pixel centres 256 p + 128 within [min, max]: p in [ceil((min-128)/256), floor((max-128)/256)]
+      int pxa = -((-(xmin - 128)) >> 8), pxb = (xmax - 128) >> 8;
+      int pya = -((-(ymin - 128)) >> 8), pyb = (ymax - 128) >> 8;
+      pxa = max(pxa, 0);
+      pya = max(pya, 0);
+      pxb = min(pxb, vw.W - 1);
+      pyb = min(pyb, vw.H - 1);
+      if (pxa <= pxb && pya <= pyb) {
+        bb.x0 = (short)pxa;
+        bb.x1 = (short)pxb;
+        bb.y0 = (short)pya;
+        bb.y1 = (short)pyb;
+        const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
+        const long long base = tile_base[vi];
+        for (int ty = pya >> th_log2; ty <= (pyb >> th_log2); ++ty)
+          for (int tx = pxa >> tw_log2; tx <= (pxb >> tw_log2); ++tx)
+            atomicAdd(count + base + (long long)ty * tiles_x + tx, 1);
+      }
+    }
+    bbox[g] = bb;
+  }
+  // one atomic per wave for the culled count
+  unsigned long long m = __ballot(culled);
+  if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd((unsigned long long*)status + 1, (unsigned long long)__popcll(m));
+}
+
+// ----------------------------------------------------------------- scan
+// Exclusive scan of count[0..n) into offs[0..n], offs[n] = total.  Blocks of
+// 256 threads x 4 items.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int block_excl_scan_256(int x, int* s_wave, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = wave_incl_scan(x);
+  if (lane == 63) s_wave[w] = inc;
+  __syncthreads();
+  int pre = 0;
+  for (int i = 0; i < w; ++i) pre += s_wave[i];
+  total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  __syncthreads();
+  return pre + inc - x;
+}
+
+__global__ void __launch_bounds__(256) k_scan_partial(const int* __restrict__ count, long long n,
+                                                      int* __restrict__ part) {
+  __shared__ int s_wave[4];
+  const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
+  int s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    if (base + j < n) s += count[base + j];
+  int total;
+  block_excl_scan_256(s, s_wave, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(256) k_scan_parts(int* __restrict__ part, long long n_part) {
+  __shared__ int s_wave[4];
+  __shared__ int s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (long long b = 0; b < n_part; b += 256) {
+    const long long i = b + threadIdx.x;
+    int x = i < n_part ? part[i] : 0;
+    int total;
+    int ex = block_excl_scan_256(x, s_wave, total);
+    const int carry = s_carry;
+    if (i < n_part) part[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry = carry + total;
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ count, long long n,
+                                                    const int* __restrict__ part, int* __restrict__ offs,
+                                                    long long* __restrict__ status) {
+  __shared__ int s_wave[4];
+  const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
+  int c[4], s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    c[j] = base + j < n ? count[base + j] : 0;
+    s += c[j];
+  }
+  int total;
+  int ex = block_excl_scan_256(s, s_wave, total) + part[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) offs[base + j] = ex;
+    ex += c[j];
+    if (base + j == n - 1) {
+      offs[n] = ex;
+      status[2] = ex;
+    }
+  }
+}
+
+// ----------------------------------------------------------------- fill
+__global__ void __launch_bounds__(256) k_fill(const mer_view* __restrict__ views, int n_views,
+                                              const long long* __restrict__ tri_base,
+                                              const long long* __restrict__ tile_base, long long total_tris,
+                                              int tw_log2, int th_log2, const BBox* __restrict__ bbox,
+                                              int* __restrict__ count, const int* __restrict__ offs,
+                                              long long bin_cap, int* __restrict__ bins) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total_tris) return;
+  const BBox bb = bbox[g];
+  if (bb.x0 > bb.x1) return;
+  const int vi = find_bucket(tri_base, n_views, g);
+  const mer_view vw = views[vi];
+  const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
+  const long long base = tile_base[vi];
+  for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
+    for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx) {
+      const long long tile = base + (long long)ty * tiles_x + tx;
+      const int slot = atomicSub(count + tile, 1) - 1;
+      const long long pos = (long long)offs[tile] + slot;
+      if (pos < bin_cap) bins[pos] = (int)g;
+    }
+}
+
+// --------------------------------------------------------------- raster
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ views, int n_views,
+                                                   const long long* __restrict__ tri_base,
+                                                   const long long* __restrict__ tile_base,
+                                                   const Rec* __restrict__ rec, const BBox* __restrict__ bbox,
+                                                   const int* __restrict__ offs, const int* __restrict__ bins,
+                                                   long long bin_cap, int32_t* __restrict__ tri_id,
+                                                   float* __restrict__ depth, float* __restrict__ bary,
+                                                   long long* __restrict__ status) {
+  constexpr int NT = TW * TH;
+  __shared__ Rec s_rec[NT];
+  __shared__ int s_tid[NT];
+  const long long g = blockIdx.x;
+  const int vi = find_bucket(tile_base, n_views, g);
+  const mer_view vw = views[vi];
+  const long long local = g - tile_base[vi];
+  const int tiles_x = (vw.W + TW - 1) / TW;
+  const int x0 = (int)(local % tiles_x) * TW, y0 = (int)(local / tiles_x) * TH;
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int px = x0 + lx, py = y0 + ly;
+  const bool inside = px < vw.W && py < vw.H;
+  const long long tb = tri_base[vi];
+
+  const long long start = offs[g], end = offs[g + 1];
+  const bool overflow = end > bin_cap;
+  // overflow fallback: scan every record of the view, filtered by bbox
+  const long long n_items = overflow ? (tri_base[vi + 1] - tb) : (end - start);
+  if (overflow && threadIdx.x == 0) atomicAdd((unsigned long long*)status, 1ull);
+
+  unsigned long long best = 0ull;
+  for (long long c0 = 0; c0 < n_items; c0 += NT) {
+    const int n = (int)min((long long)NT, n_items - c0);
+    if (threadIdx.x < n) {
+      long long r;
+      bool keep = true;
+      if (!overflow) {
+        r = bins[start + c0 + threadIdx.x];
+      } else {
+        r = tb + c0 + threadIdx.x;
+        const BBox bb = bbox[r];
+        keep = bb.x0 <= bb.x1 && bb.x1 >= x0 && bb.x0 < x0 + TW && bb.y1 >= y0 && bb.y0 < y0 + TH;
+      }
+      s_tid[threadIdx.x] = keep ? (int)(r - tb) : -1;
+      if (keep) s_rec[threadIdx.x] = rec[r];
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+      const int t = s_tid[j];
+      if (t < 0) continue;  // uniform across the block
+      const Rec& R = s_rec[j];
+      long long E[3];
+      edge_eval(R, px, py, E);
+      const bool cov = inside && covered(E);
+      if (__ballot(cov)) {
+        if (cov) {
+          float e[3], d;
+          edge_values(R, E, e, d);
+          const float q = depth_key(R, e, d);
+          const unsigned long long k = vis_key(q, t);
+          best = k > best ? k : best;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (!inside) return;
+  const long long p = vw.px_off + (long long)py * vw.W + px;
+  const int t = key_tri(best);
+  tri_id[p] = t;
+  if (depth) depth[p] = t >= 0 ? 1.0f / key_q(best) : 0.0f;
+  if (bary) {
+    float b0 = 0.f, b1 = 0.f;
+    if (t >= 0) {
+      const Rec R = rec[tb + t];
+      long long E[3];
+      edge_eval(R, px, py, E);
+      float e[3], d;
+      edge_values(R, E, e, d);
+      float w[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) w[k] = (e[k] / d) * R.q[k];
+      const float W = (w[0] + w[1]) + w[2];
+      b0 = w[0] / W;
+      b1 = w[1] / W;
+    }
+    bary[2 * p] = b0;
+    bary[2 * p + 1] = b1;
+  }
+}
+
+// --------------------------------------------------------------- launch
+int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, int32_t* tri_id,
+                     float* depth, float* bary, void* ws, hipStream_t st) {
+  char* w = (char*)ws;
+  long long* viewtab = (long long*)(w + P->off_viewtab);
+  long long* tri_base = viewtab;
+  long long* tile_base = viewtab + (P->n_views + 1);
+  Rec* rec = (Rec*)(w + P->off_rec);
+  BBox* bbox = (BBox*)(w + P->off_bbox);
+  int* count = (int*)(w + P->off_count);
+  int* offs = (int*)(w + P->off_offs);
+  int* part = (int*)(w + P->off_part);
+  int* bins = (int*)(w + P->off_bins);
+  long long* status = (long long*)(w + P->off_status);
+  const int twl = __builtin_ctz(P->tile_w), thl = __builtin_ctz(P->tile_h);
+
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, twl, thl, tri_base, tile_base, status);
+  const long long nt = P->total_tiles;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)min((nt + 255) / 256, 4096ll)), dim3(256), 0, st, count, nt);
+  if (P->total_tris > 0) {
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+                       v, tri, tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, status);
+  }
+  hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part);
+  hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(256), 0, st, part, P->n_part);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part, offs, status);
+  if (P->total_tris > 0) {
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+                       tri_base, tile_base, P->total_tris, twl, thl, bbox, count, offs, P->bin_cap, bins);
+  }
+#define MER_RASTER(TW, TH)                                                                                       \
+  hipLaunchKernelGGL((k_raster<TW, TH>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views, P->n_views, tri_base, \
+                     tile_base, rec, bbox, offs, bins, P->bin_cap, tri_id, depth, bary, status)
+  if (P->tile_w == 8 && P->tile_h == 8) MER_RASTER(8, 8);
+  else if (P->tile_w == 16 && P->tile_h == 16) MER_RASTER(16, 16);
+  else if (P->tile_w == 32 && P->tile_h == 8) MER_RASTER(32, 8);
+  else if (P->tile_w == 16 && P->tile_h == 8) MER_RASTER(16, 8);
+  else return MER_ETUNING;
+#undef MER_RASTER
+  return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
+}
+
+}  // namespace mer

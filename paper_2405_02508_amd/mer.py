@@ -1,0 +1,252 @@
+"""Thin Python binding of ``libmer.so`` (include/mer.h) -- argument marshalling only.
+
+Every step of the path runs in the HIP kernels behind the C ABI; this module
+only checks tensor dtypes/devices, passes ``data_ptr()`` and the current
+stream, and turns error codes into exceptions.  If the library has not been
+built it raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmer.so")
+
+NO_INTERSECT = 1
+SKIP_EDGE = 2
+SKIP_INTERP = 4
+
+SYMBOLS = ("mer_plan_init", "mer_rasterize", "mer_interpolate", "mer_edge_grad", "mer_interpolate_bwd",
+           "mer_backward_fused", "mer_status", "mer_strerror", "mer_version")
+
+
+class View(ctypes.Structure):
+    _fields_ = [("v_off", ctypes.c_int64), ("t_off", ctypes.c_int64), ("a_off", ctypes.c_int64),
+                ("px_off", ctypes.c_int64), ("n_v", ctypes.c_int32), ("n_t", ctypes.c_int32),
+                ("H", ctypes.c_int32), ("W", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("bin_cap", ctypes.c_int64)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("n_views", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("total_tris", ctypes.c_int64), ("total_tiles", ctypes.c_int64),
+                ("total_px", ctypes.c_int64), ("bin_cap", ctypes.c_int64), ("px_begin", ctypes.c_int64),
+                ("ws_bytes", ctypes.c_int64),
+                ("off_viewtab", ctypes.c_int64), ("off_rec", ctypes.c_int64), ("off_bbox", ctypes.c_int64),
+                ("off_count", ctypes.c_int64), ("off_offs", ctypes.c_int64), ("off_part", ctypes.c_int64),
+                ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("n_part", ctypes.c_int64)]
+
+
+class MerError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libmer.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MerError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+        L.mer_plan_init.argtypes = [ctypes.POINTER(View), i, ctypes.POINTER(Tuning), ctypes.POINTER(Plan)]
+        L.mer_rasterize.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, P]
+        L.mer_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, P, i, P, P]
+        L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P]
+        L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P]
+        L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P]
+        L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
+        L.mer_strerror.argtypes = [i]
+        L.mer_strerror.restype = ctypes.c_char_p
+        L.mer_version.restype = i
+        for name in SYMBOLS:
+            getattr(L, name).restype = getattr(L, name).restype or i
+        L.mer_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise MerError(f"mer error {rc}: {lib().mer_strerror(rc).decode()}")
+
+
+def views_struct(views_i64: np.ndarray):
+    """int64 [n, 8] table (v_off, t_off, a_off, px_off, n_v, n_t, H, W) -> ctypes array of View."""
+    views_i64 = np.asarray(views_i64, np.int64)
+    arr = (View * views_i64.shape[0])()
+    for i, r in enumerate(views_i64):
+        arr[i] = View(*[int(x) for x in r])
+    return arr
+
+
+def plan_init(views_i64, tile=(8, 8), bin_cap=0) -> Plan:
+    vs = views_struct(views_i64)
+    tun = Tuning(int(tile[0]), int(tile[1]), int(bin_cap))
+    P = Plan()
+    _check(lib().mer_plan_init(vs, len(vs), ctypes.byref(tun), ctypes.byref(P)))
+    return P
+
+
+# ------------------------------------------------------------------ torch side
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    import torch
+    if t is None:
+        raise MerError(f"{name} is required")
+    if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+        raise MerError(f"{name} must be a contiguous {dtype} CUDA tensor (got {t.dtype}, {t.device})")
+    return t
+
+
+class Context:
+    """Plan + device view table + workspace for one batch of views.
+
+    Owns nothing but torch tensors; every method is one C-ABI call on the
+    current torch stream.
+    """
+
+    def __init__(self, views_i64, device="cuda", tile=(8, 8), bin_cap=0):
+        import torch
+        self.views_i64 = np.asarray(views_i64, np.int64)
+        self.plan = plan_init(self.views_i64, tile, bin_cap)
+        raw = bytes(views_struct(self.views_i64))
+        self.views_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self.ws = torch.empty(int(self.plan.ws_bytes), dtype=torch.uint8, device=device)
+        self.n_px = int(self.plan.total_px)
+        self.tile = tuple(tile)
+        V = self.views_i64
+        self.need_v = int((V[:, 0] + V[:, 4]).max())
+        self.need_t = int((V[:, 1] + V[:, 5]).max())
+        self.need_a = int((V[:, 2] + V[:, 4]).max())
+
+    def _rows(self, t, n, name, cols=None):
+        if t is None:
+            return
+        if t.shape[0] < n or (cols is not None and (t.dim() != 2 or t.shape[1] != cols)):
+            raise MerError(f"{name} has shape {tuple(t.shape)}; the view table needs {n} rows"
+                           + (f" x {cols}" if cols else ""))
+
+    def _geom(self, v, tri, attr=None):
+        import torch
+        _need(v, torch.float32, "v")
+        _need(tri, torch.int32, "tri")
+        if attr is not None:
+            _need(attr, torch.float32, "attr")
+        self._rows(v, self.need_v, "v", 3)
+        self._rows(tri, self.need_t, "tri", 3)
+        self._rows(attr, self.need_a, "attr")
+
+    def _px(self, t, name, cols=None):
+        if t is not None:
+            if t.shape[0] < self.n_px or (cols is not None and (t.dim() != 2 or t.shape[1] != cols)):
+                raise MerError(f"{name} has shape {tuple(t.shape)}; needs {self.n_px} pixel rows"
+                               + (f" x {cols}" if cols else ""))
+
+    # forward --------------------------------------------------------------
+    def rasterize(self, v, tri, tri_id, depth=None, bary=None):
+        import torch
+        _need(v, torch.float32, "v")
+        _need(tri, torch.int32, "tri")
+        _need(tri_id, torch.int32, "tri_id")
+        if depth is not None:
+            _need(depth, torch.float32, "depth")
+        if bary is not None:
+            _need(bary, torch.float32, "bary")
+        self._geom(v, tri)
+        self._px(tri_id, "tri_id")
+        self._px(depth, "depth")
+        self._px(bary, "bary", 2)
+        _check(lib().mer_rasterize(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
+                                   _ptr(depth), _ptr(bary), _ptr(self.ws), _stream()))
+
+    def interpolate(self, attr, v, tri, tri_id, out, bary=None, append_z=False):
+        import torch
+        _need(attr, torch.float32, "attr")
+        _need(out, torch.float32, "out")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(out, "out", int(attr.shape[1]) + int(bool(append_z)))
+        if bary is not None:
+            _need(bary, torch.float32, "bary")
+            self._px(bary, "bary", 2)
+        _check(lib().mer_interpolate(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(attr), int(attr.shape[1]),
+                                     _ptr(v), _ptr(tri), _ptr(tri_id), _ptr(bary), int(bool(append_z)), _ptr(out),
+                                     _stream()))
+
+    # backward -------------------------------------------------------------
+    def edge_grad(self, v, tri, tri_id, img, g_img, g_v, flags=0):
+        import torch
+        _need(img, torch.float32, "img")
+        _need(g_img, torch.float32, "g_img")
+        _need(g_v, torch.float32, "g_v")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri)
+        self._rows(g_v, self.need_v, "g_v", 3)
+        self._px(tri_id, "tri_id")
+        self._px(img, "img")
+        self._px(g_img, "g_img", int(img.shape[1]))
+        _check(lib().mer_edge_grad(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
+                                   _ptr(img), _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_v), _stream()))
+
+    def interpolate_bwd(self, attr, v, tri, tri_id, g_out, g_attr=None, g_v=None, append_z=False):
+        import torch
+        _need(g_out, torch.float32, "g_out")
+        _need(attr, torch.float32, "attr")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(g_out, "g_out")
+        if g_attr is not None:
+            _need(g_attr, torch.float32, "g_attr")
+            self._rows(g_attr, self.need_a, "g_attr", int(attr.shape[1]))
+        if g_v is not None:
+            _need(g_v, torch.float32, "g_v")
+            self._rows(g_v, self.need_v, "g_v", 3)
+        _check(lib().mer_interpolate_bwd(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(attr),
+                                         int(attr.shape[1]), _ptr(v), _ptr(tri), _ptr(tri_id), int(bool(append_z)),
+                                         _ptr(g_out), int(g_out.shape[1]), _ptr(g_attr), _ptr(g_v), _stream()))
+
+    def backward(self, v, tri, tri_id, attr, img, g_img, g_attr, g_v, append_z=False, flags=0):
+        import torch
+        _need(img, torch.float32, "img")
+        _need(g_img, torch.float32, "g_img")
+        _need(attr, torch.float32, "attr")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(img, "img")
+        self._px(g_img, "g_img", int(img.shape[1]))
+        if g_attr is not None:
+            _need(g_attr, torch.float32, "g_attr")
+            self._rows(g_attr, self.need_a, "g_attr", int(attr.shape[1]))
+        if g_v is not None:
+            _need(g_v, torch.float32, "g_v")
+            self._rows(g_v, self.need_v, "g_v", 3)
+        _check(lib().mer_backward_fused(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri),
+                                        _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
+                                        _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_attr), _ptr(g_v),
+                                        _stream()))
+
+    def status(self):
+        out = (ctypes.c_int64 * 4)()
+        _check(lib().mer_status(ctypes.byref(self.plan), _ptr(self.ws), _stream(), out))
+        return dict(overflow_tiles=out[0], culled=out[1], entries=out[2], bin_cap=out[3])

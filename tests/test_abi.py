@@ -1,0 +1,92 @@
+"""The C-ABI library loads and exports what include/mer.h declares; the
+host-only plan call validates its inputs.  No GPU needed."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2405_02508_amd import mer
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mer.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(mer.LIB_PATH):
+        from paper_2405_02508_amd import build
+        build.build()
+    return mer.lib()
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mer_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert set(declared()) == set(mer.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    out = subprocess.run(["nm", "-D", "--defined-only", mer.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mer_\w+)", out))
+    for name in declared():
+        assert name in exported, name
+        assert hasattr(L, name)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    c = tmp_path / "lay.c"
+    c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mer.h"\nint main(void){'
+                 'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mer_view), sizeof(mer_tuning), sizeof(mer_plan),'
+                 'offsetof(mer_view,n_v), offsetof(mer_plan,ws_bytes), offsetof(mer_plan,n_part));return 0;}')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    want = [ctypes.sizeof(mer.View), ctypes.sizeof(mer.Tuning), ctypes.sizeof(mer.Plan),
+            mer.View.n_v.offset, mer.Plan.ws_bytes.offset, mer.Plan.n_part.offset]
+    assert got == want
+
+
+def test_version_and_strerror(L):
+    assert L.mer_version() >= 1
+    assert L.mer_strerror(0) == b"ok"
+    assert b"invalid" in L.mer_strerror(-1)
+
+
+def _views(rows):
+    return np.array(rows, np.int64)
+
+
+def test_plan_totals_and_layout(L):
+    V = _views([[0, 0, 0, 0, 10, 20, 17, 33], [10, 0, 0, 17 * 33, 10, 20, 8, 8]])
+    P = mer.plan_init(V, (8, 8))
+    assert P.total_tris == 40 and P.total_px == 17 * 33 + 64
+    assert P.total_tiles == 3 * 5 + 1
+    offs = [P.off_viewtab, P.off_rec, P.off_bbox, P.off_count, P.off_offs, P.off_part, P.off_bins, P.off_status]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs) and P.ws_bytes > offs[-1]
+    assert P.bin_cap > 0
+    P2 = mer.plan_init(V, (16, 16), bin_cap=5)
+    assert P2.bin_cap == 5 and P2.total_tiles == 2 * 3 + 1
+
+
+@pytest.mark.parametrize("bad", [
+    [[0, 0, 0, 0, 3, 1, 0, 8]],          # H = 0
+    [[0, 0, 0, 0, 3, 1, 8, 40000]],      # W too large
+    [[0, 0, 0, 0, -1, 1, 8, 8]],         # negative n_v
+    [[0, 0, 0, 64, 3, 1, 8, 8], [0, 0, 0, 0, 3, 1, 8, 8]],   # views out of order
+    [[0, 0, 0, 0, 3, 1, 8, 8], [0, 0, 0, 60, 3, 1, 8, 8]],   # overlapping pixels
+])
+def test_plan_rejects_bad_views(L, bad):
+    with pytest.raises(mer.MerError, match="-1"):
+        mer.plan_init(_views(bad))
+
+
+def test_plan_rejects_bad_tile(L):
+    with pytest.raises(mer.MerError, match="-4"):
+        mer.plan_init(_views([[0, 0, 0, 0, 3, 1, 8, 8]]), (4, 4))
