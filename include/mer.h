@@ -63,22 +63,29 @@ typedef struct mer_view {
   int32_t n_v, n_t, H, W;
 } mer_view;       /* 48 bytes, no padding */
 
-/* Tile shape (pixels) and bin pool capacity (triangle-tile entries; 0 picks
- * a default from the triangle and tile counts). */
+/* Tile shape (pixels), bin pool capacity (triangle-tile entries; 0 picks a
+ * default from the triangle and tile counts) and the small-triangle limit:
+ * a triangle whose box of pixel centres holds at most small_px centres is
+ * rasterized by its set-up thread directly into the per-pixel z-buffer key
+ * instead of being binned (0 picks the default 16, a negative value bins
+ * every triangle).  The results do not depend on any of these. */
 typedef struct mer_tuning {
   int32_t tile_w, tile_h; /* supported: 8x8, 16x16, 32x8, 16x8 */
   int64_t bin_cap;
+  int32_t small_px;
+  int32_t reserved; /* set to 0 */
 } mer_tuning;
 
 /* Host-side plan: totals over the view table and the workspace layout.
  * Filled by mer_plan_init; treat as opaque apart from ws_bytes. */
 typedef struct mer_plan {
-  int32_t n_views, tile_w, tile_h, pad0;
+  int32_t n_views, tile_w, tile_h, small_px;
   int64_t total_tris, total_tiles, total_px, bin_cap;
   int64_t px_begin; /* first pixel of the first view (pixel kernels cover [px_begin, total_px)) */
   int64_t ws_bytes;
-  int64_t off_viewtab, off_rec, off_bbox, off_count, off_offs, off_part, off_bins, off_status;
+  int64_t off_viewtab, off_rec, off_bbox, off_count, off_offs, off_part, off_bins, off_status, off_key;
   int64_t n_part;
+  int64_t total_btiles, off_bviewtab; /* 16x16 tiles of the backward sweep */
 } mer_plan;
 
 /* Validate the host copy of the view table (H, W in [1, 32767], n_v, n_t >= 0,
@@ -109,7 +116,8 @@ int mer_rasterize(const mer_plan *plan, const mer_view *views_dev, const float *
  * append_z, out[p, C_a] = sum_k b_k z_k (screen z of the view's vertices);
  * 0 on background.  bary may be NULL: the barycentrics are then recomputed
  * from tri_id and v exactly as mer_rasterize computes them.
- *   attr: float [*, C_a] (1 <= C_a <= 64).  out: float [total_px, C_a+append_z]. */
+ *   attr: float [*, C_a] (1 <= C_a, C_a + append_z <= 64).
+ *   out: float [total_px, C_a+append_z]. */
 int mer_interpolate(const mer_plan *plan, const mer_view *views_dev, const float *attr, int C_a,
                     const float *v, const int32_t *tri, const int32_t *tri_id, const float *bary,
                     int append_z, float *out, void *stream);
@@ -132,7 +140,7 @@ int mer_interpolate(const mer_plan *plan, const mer_view *views_dev, const float
  *   [sum n_v, 3], accumulated.  flags: MER_NO_INTERSECT. */
 int mer_edge_grad(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
                   const int32_t *tri_id, const float *img, const float *g_img, int C_e, int flags,
-                  float *g_v, void *stream);
+                  float *g_v, void *ws, void *stream);
 
 /* Backward of mer_interpolate (supplement: "straightforward differentiation
  * of the forward pass"), the smooth term Omega of Sec. 3:
@@ -144,16 +152,23 @@ int mer_edge_grad(const mer_plan *plan, const mer_view *views_dev, const float *
  *   g_attr: float [*, C_a] accumulated, may be NULL; g_v may be NULL. */
 int mer_interpolate_bwd(const mer_plan *plan, const mer_view *views_dev, const float *attr, int C_a,
                         const float *v, const int32_t *tri, const int32_t *tri_id, int append_z,
-                        const float *g_out, int ld_out, float *g_attr, float *g_v, void *stream);
+                        const float *g_out, int ld_out, float *g_attr, float *g_v, void *ws, void *stream);
 
 /* Both backward passes in one sweep over the pixels: the EdgeGrad term on
  * (img, g_img, C_e) and the interpolation adjoint on the first C_a+append_z
  * channels of g_img (so the interpolated attributes must be the first
  * channels of the image).  flags: MER_NO_INTERSECT, MER_SKIP_EDGE,
- * MER_SKIP_INTERP. */
+ * MER_SKIP_INTERP.
+ *
+ * The three backward calls sweep 16x16 pixel tiles; each workgroup sums its
+ * contributions per vertex in LDS before the global float atomics.  They use
+ * the plan's workspace `ws` only for a small view/tile table (rewritten on
+ * every call), so a backward call may follow mer_rasterize on the same
+ * stream with the same workspace. */
 int mer_backward_fused(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
                        const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
-                       const float *g_img, int C_e, int flags, float *g_attr, float *g_v, void *stream);
+                       const float *g_img, int C_e, int flags, float *g_attr, float *g_v, void *ws,
+                       void *stream);
 
 /* Wait for `stream`, then read the workspace status of the last
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool

@@ -1,0 +1,140 @@
+"""torch.autograd wrappers over the C ABI (argument marshalling only).
+
+The module split follows the paper's implementation (supplement,
+"Implementation detail"): rasterization has no backward; interpolation has
+one (the smooth term Omega); EdgeGrad is the identity in the forward pass
+and computes dL/d(vertex positions) from the micro-edges in its backward
+pass.  ``RenderStep`` fuses all three for one call per optimisation step:
+its forward rasterizes and interpolates every view, its backward runs the
+fused micro-edge + interpolation sweep once.
+
+Screen vertices are per view (rows v_off .. v_off + n_v of ``v``); a world
+to screen transform written with torch ops in front of these functions
+reduces the per-view screen gradients to world space through autograd.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import mer
+
+
+class Renderer:
+    """Plan, workspace and topology for a fixed view table."""
+
+    def __init__(self, views_i64, tri, device="cuda", tile=(8, 8), small_px=0, bin_cap=0,
+                 append_z=False, mask_channel=False, store_bary=True):
+        self.ctx = mer.Context(views_i64, device=device, tile=tile, bin_cap=bin_cap, small_px=small_px)
+        self.tri = tri if isinstance(tri, torch.Tensor) else torch.from_numpy(tri).to(device)
+        self.n_px = self.ctx.n_px
+        self.append_z = bool(append_z)
+        self.mask_channel = bool(mask_channel)
+        self.store_bary = bool(store_bary)
+        self.device = torch.device(device)
+
+    def rasterize(self, v):
+        """Index image, depth and (optionally) barycentrics; no gradient."""
+        tid = torch.empty(self.n_px, dtype=torch.int32, device=self.device)
+        depth = torch.empty(self.n_px, dtype=torch.float32, device=self.device)
+        bary = torch.empty(self.n_px, 2, dtype=torch.float32, device=self.device) if self.store_bary else None
+        self.ctx.rasterize(v.detach().contiguous(), self.tri, tid, depth, bary)
+        return tid, depth, bary
+
+
+class Interpolate(torch.autograd.Function):
+    """out = sum_k b_k attr_k (+ interpolated z); backward: attr and Omega to v."""
+
+    @staticmethod
+    def forward(ctx, v, attr, tid, bary, r: Renderer):
+        C = attr.shape[1] + int(r.append_z)
+        out = torch.empty(r.n_px, C, dtype=torch.float32, device=v.device)
+        r.ctx.interpolate(attr.detach().contiguous(), v.detach().contiguous(), r.tri, tid, out, bary=bary,
+                          append_z=r.append_z)
+        ctx.save_for_backward(v, attr, tid)
+        ctx.r = r
+        ctx.mark_non_differentiable(tid)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out):
+        v, attr, tid = ctx.saved_tensors
+        r = ctx.r
+        g_v = torch.zeros_like(v) if ctx.needs_input_grad[0] else None
+        g_attr = torch.zeros_like(attr) if ctx.needs_input_grad[1] else None
+        if g_v is not None or g_attr is not None:
+            r.ctx.interpolate_bwd(attr.detach().contiguous(), v.detach().contiguous(), r.tri, tid,
+                                  g_out.contiguous(), g_attr, g_v, append_z=r.append_z)
+        return g_v, g_attr, None, None, None
+
+
+class EdgeGrad(torch.autograd.Function):
+    """Identity on the image; backward adds the micro-edge term to dL/dv and
+    passes dL/dimage through unchanged (supplement, "EdgeGrad module")."""
+
+    @staticmethod
+    def forward(ctx, img, v, tid, r: Renderer, flags: int = 0):
+        ctx.save_for_backward(img, v, tid)
+        ctx.r = r
+        ctx.flags = flags
+        return img.view_as(img)
+
+    @staticmethod
+    def backward(ctx, g_img):
+        img, v, tid = ctx.saved_tensors
+        g_v = None
+        if ctx.needs_input_grad[1]:
+            g_v = torch.zeros_like(v)
+            ctx.r.ctx.edge_grad(v.detach().contiguous(), ctx.r.tri, tid, img.detach().contiguous(),
+                                g_img.contiguous(), g_v, flags=ctx.flags)
+        return g_img, g_v, None, None, None
+
+
+class RenderStep(torch.autograd.Function):
+    """One call per step: image = [interpolated attributes (+ z), (mask)] with
+    the EdgeGrad identity folded in; backward = one fused sweep."""
+
+    @staticmethod
+    def forward(ctx, v, attr, r: Renderer, flags: int = 0):
+        vd, ad = v.detach().contiguous(), attr.detach().contiguous()
+        tid, depth, bary = r.rasterize(vd)
+        C = attr.shape[1] + int(r.append_z)
+        C_e = C + int(r.mask_channel)
+        img = torch.empty(r.n_px, C_e, dtype=torch.float32, device=v.device)
+        if C_e == C:
+            r.ctx.interpolate(ad, vd, r.tri, tid, img, bary=bary, append_z=r.append_z)
+        else:
+            tmp = torch.empty(r.n_px, C, dtype=torch.float32, device=v.device)
+            r.ctx.interpolate(ad, vd, r.tri, tid, tmp, bary=bary, append_z=r.append_z)
+            img[:, :C].copy_(tmp)
+            img[:, C].copy_(tid >= 0)
+        ctx.save_for_backward(vd, ad, tid, img)
+        ctx.r = r
+        ctx.flags = flags
+        ctx.mark_non_differentiable(tid, depth)
+        return img, tid, depth
+
+    @staticmethod
+    def backward(ctx, g_img, _g_tid, _g_depth):
+        v, attr, tid, img = ctx.saved_tensors
+        r = ctx.r
+        g_v = torch.zeros_like(v)
+        g_attr = torch.zeros_like(attr)
+        r.ctx.backward(v, r.tri, tid, attr, img, g_img.contiguous(), g_attr, g_v, append_z=r.append_z,
+                       flags=ctx.flags)
+        return (g_v if ctx.needs_input_grad[0] else None, g_attr if ctx.needs_input_grad[1] else None, None, None)
+
+
+def render(v, attr, r: Renderer, flags: int = 0):
+    """Fused forward (image, tri_id, depth); gradients flow to v and attr."""
+    return RenderStep.apply(v, attr, r, flags)
+
+
+def project(v_world, R, C, f, cx, cy):
+    """World points [V,3] -> per-view screen vertices [n_cam * V, 3] (torch ops,
+    differentiable): camera frame rows R [n,3,3], centres C [n,3], focal f
+    [n], principal point (cx, cy) [n]."""
+    pc = torch.einsum("nij,vj->nvi", R, v_world) - torch.einsum("nij,nj->ni", R, C)[:, None, :]
+    z = pc[..., 2]
+    x = f[:, None] * pc[..., 0] / z + cx[:, None]
+    y = f[:, None] * pc[..., 1] / z + cy[:, None]
+    return torch.stack([x, y, z], -1).reshape(-1, 3)

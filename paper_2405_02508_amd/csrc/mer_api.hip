@@ -37,7 +37,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   const int tw = tun ? tun->tile_w : 8, th = tun ? tun->tile_h : 8;
   if (!tile_supported(tw, th)) return MER_ETUNING;
   memset(P, 0, sizeof(*P));
-  int64_t tris = 0, tiles = 0, px_end = 0;
+  int64_t tris = 0, tiles = 0, btiles = 0, px_end = 0;
   for (int i = 0; i < n_views; ++i) {
     const mer_view& w = views[i];
     if (w.H < 1 || w.W < 1 || w.H > 32767 || w.W > 32767) return MER_EINVAL;
@@ -46,18 +46,21 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
     px_end = w.px_off + (int64_t)w.H * w.W;
     tris += w.n_t;
     tiles += (int64_t)((w.W + tw - 1) / tw) * ((w.H + th - 1) / th);
+    btiles += (int64_t)((w.W + 15) / 16) * ((w.H + 15) / 16);
   }
   if (tris > INT_MAX) return MER_EINVAL;
   P->n_views = n_views;
+  P->px_begin = views[0].px_off;
   P->tile_w = tw;
   P->tile_h = th;
   P->total_tris = tris;
   P->total_tiles = tiles;
+  P->total_btiles = btiles;
   P->total_px = px_end;
-  P->px_begin = views[0].px_off;
   int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 4 * tris + 16 * tiles + 4096;
   if (cap > INT_MAX) cap = INT_MAX;
   P->bin_cap = cap;
+  P->small_px = (tun && tun->small_px != 0) ? (tun->small_px < 0 ? 0 : tun->small_px) : 16;
   P->n_part = (tiles + 1023) / 1024;
   int64_t off = 0;
   P->off_viewtab = off;
@@ -76,6 +79,10 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   off = align256(off + cap * 4);
   P->off_status = off;
   off = align256(off + 8 * 8);
+  P->off_key = off;
+  off = align256(off + (px_end - P->px_begin) * 8);
+  P->off_bviewtab = off;
+  off = align256(off + 2 * (int64_t)(n_views + 1) * 8);
   P->ws_bytes = off;
   return MER_OK;
 }
@@ -94,7 +101,8 @@ int mer_rasterize(const mer_plan* P, const mer_view* views_dev, const float* v, 
 int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,
                     const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
                     void* stream) {
-  if (!plan_ok(P) || !views_dev || !attr || !tri || !tri_id || !out || C_a < 1 || C_a > 64) return MER_EINVAL;
+  if (!plan_ok(P) || !views_dev || !attr || !tri || !tri_id || !out || C_a < 1 || C_a + (append_z ? 1 : 0) > 64)
+    return MER_EINVAL;
   if ((append_z || !bary) && !v) return MER_EINVAL;
   return mer::launch_interpolate(P, views_dev, attr, C_a, v, tri, tri_id, bary, append_z ? 1 : 0, out,
                                  (hipStream_t)stream);
@@ -102,33 +110,36 @@ int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* a
 
 int mer_edge_grad(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
                   const int32_t* tri_id, const float* img, const float* g_img, int C_e, int flags, float* g_v,
-                  void* stream) {
+                  void* ws, void* stream) {
   if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !img || !g_img || !g_v || C_e < 1 || C_e > 64)
     return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, nullptr, 0, 0, img, g_img, C_e, C_e,
-                              (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, (hipStream_t)stream);
+                              (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, ws, (hipStream_t)stream);
 }
 
 int mer_interpolate_bwd(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,
                         const int32_t* tri, const int32_t* tri_id, int append_z, const float* g_out, int ld_out,
-                        float* g_attr, float* g_v, void* stream) {
+                        float* g_attr, float* g_v, void* ws, void* stream) {
   const int C = C_a + (append_z ? 1 : 0);
   if (!plan_ok(P) || !views_dev || !attr || !v || !tri || !tri_id || !g_out || C_a < 1 || C_a > 64 || ld_out < C)
     return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
   if (!g_attr && !g_v) return MER_OK;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, nullptr, g_out, ld_out,
-                              ld_out, MER_SKIP_EDGE, g_attr, g_v, (hipStream_t)stream);
+                              ld_out, MER_SKIP_EDGE, g_attr, g_v, ws, (hipStream_t)stream);
 }
 
 int mer_backward_fused(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
                        const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
-                       const float* g_img, int C_e, int flags, float* g_attr, float* g_v, void* stream) {
+                       const float* g_img, int C_e, int flags, float* g_attr, float* g_v, void* ws, void* stream) {
   const int C = C_a + (append_z ? 1 : 0);
   if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !g_img || C_e < 1 || C_e > 64) return MER_EINVAL;
   if (!(flags & MER_SKIP_EDGE) && (!img || !g_v)) return MER_EINVAL;
   if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, g_img, C_e, C_e,
-                              flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr, g_v,
+                              flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr, g_v, ws,
                               (hipStream_t)stream);
 }
 

@@ -7,61 +7,89 @@
 namespace mer {
 
 // ---------------------------------------------------------- interpolate
+// One thread per pixel computes its C values into LDS; the block then writes
+// its 256 x C floats as one contiguous span (coalesced), unless the block
+// straddles a gap between views, where each pixel writes its own values.
 __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ views, int n_views,
                                                 const float* __restrict__ attr, int C_a,
                                                 const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                 const int32_t* __restrict__ tri_id, const float* __restrict__ bary,
                                                 int append_z, float* __restrict__ out, long long px_begin,
                                                 long long total_px) {
-  const long long p = px_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= total_px) return;
-  const int vi = find_view_px(views, n_views, p);
-  const mer_view vw = views[vi];
-  const long long local = p - vw.px_off;
-  if (local < 0 || local >= (long long)vw.H * vw.W) return;
+  extern __shared__ float s_out[];
+  __shared__ int s_gap;
   const int C = C_a + append_z;
-  float* o = out + p * C;
-  int t = tri_id[p];
-  if (t >= vw.n_t) t = -1;
+  const long long p0 = px_begin + (long long)blockIdx.x * blockDim.x;
+  const long long p = p0 + threadIdx.x;
+  if (threadIdx.x == 0) s_gap = 0;
+  __syncthreads();
+  bool valid = false;
   float b0 = 0.f, b1 = 0.f, b2 = 0.f;
   int idx[3] = {0, 0, 0};
-  bool ok = false;
-  if (t >= 0) {
-    const int32_t* row = tri + (vw.t_off + t) * 3;
-    idx[0] = row[0];
-    idx[1] = row[1];
-    idx[2] = row[2];
-    ok = idx[0] >= 0 && idx[0] < vw.n_v && idx[1] >= 0 && idx[1] < vw.n_v && idx[2] >= 0 && idx[2] < vw.n_v;
-    if (ok) {
-      if (bary) {
-        b0 = bary[2 * p];
-        b1 = bary[2 * p + 1];
-        b2 = (1.0f - b0) - b1;
-      } else {
-        const Snap s = snap_triangle(v, vw, row);
-        ok = s.ok;
+  mer_view vw;
+  if (p < total_px) {
+    const int vi = find_view_px(views, n_views, p);
+    vw = views[vi];
+    const long long local = p - vw.px_off;
+    valid = local >= 0 && local < (long long)vw.H * vw.W;
+    if (valid) {
+      int t = tri_id[p];
+      if (t >= 0 && t < vw.n_t) {
+        const int32_t* row = tri + (vw.t_off + t) * 3;
+        idx[0] = row[0];
+        idx[1] = row[1];
+        idx[2] = row[2];
+        bool ok = idx[0] >= 0 && idx[0] < vw.n_v && idx[1] >= 0 && idx[1] < vw.n_v && idx[2] >= 0 &&
+                  idx[2] < vw.n_v;
         if (ok) {
-          const PixBary pb = pixel_bary(s, (int)(local % vw.W), (int)(local / vw.W));
-          b0 = pb.b[0];
-          b1 = pb.b[1];
-          b2 = pb.b[2];
+          if (bary) {
+            const float2 bb = *reinterpret_cast<const float2*>(bary + 2 * p);
+            b0 = bb.x;
+            b1 = bb.y;
+            b2 = (1.0f - b0) - b1;
+          } else {
+            const Snap sn = snap_triangle(v, vw, row);
+            ok = sn.ok;
+            if (ok) {
+              const PixBary pb = pixel_bary(sn, (int)(local % vw.W), (int)(local / vw.W));
+              b0 = pb.b[0];
+              b1 = pb.b[1];
+              b2 = pb.b[2];
+            }
+          }
         }
+        if (!ok) b0 = b1 = b2 = 0.f;
+        if (!ok) idx[0] = -1;
+      } else {
+        idx[0] = -1;
       }
+    } else {
+      atomicOr(&s_gap, 1);
     }
   }
-  if (!ok) {
-    for (int c = 0; c < C; ++c) o[c] = 0.f;
+  float* so = s_out + threadIdx.x * C;
+  if (valid && idx[0] >= 0) {
+    const float* a0 = attr + (vw.a_off + idx[0]) * C_a;
+    const float* a1 = attr + (vw.a_off + idx[1]) * C_a;
+    const float* a2 = attr + (vw.a_off + idx[2]) * C_a;
+    for (int c = 0; c < C_a; ++c) so[c] = (b0 * a0[c] + b1 * a1[c]) + b2 * a2[c];
+    if (append_z) {
+      const float z0 = v[(vw.v_off + idx[0]) * 3 + 2], z1 = v[(vw.v_off + idx[1]) * 3 + 2],
+                  z2 = v[(vw.v_off + idx[2]) * 3 + 2];
+      so[C_a] = (b0 * z0 + b1 * z1) + b2 * z2;
+    }
+  } else {
+    for (int c = 0; c < C; ++c) so[c] = 0.f;
+  }
+  __syncthreads();
+  if (s_gap) {
+    if (valid)
+      for (int c = 0; c < C; ++c) out[p * C + c] = so[c];
     return;
   }
-  const float* a0 = attr + (vw.a_off + idx[0]) * C_a;
-  const float* a1 = attr + (vw.a_off + idx[1]) * C_a;
-  const float* a2 = attr + (vw.a_off + idx[2]) * C_a;
-  for (int c = 0; c < C_a; ++c) o[c] = (b0 * a0[c] + b1 * a1[c]) + b2 * a2[c];
-  if (append_z) {
-    const float z0 = v[(vw.v_off + idx[0]) * 3 + 2], z1 = v[(vw.v_off + idx[1]) * 3 + 2],
-                z2 = v[(vw.v_off + idx[2]) * 3 + 2];
-    o[C_a] = (b0 * z0 + b1 * z1) + b2 * z2;
-  }
+  const long long n_here = min((long long)blockDim.x, total_px - p0);
+  float* dst = out + p0 * C;
+  for (long long i = threadIdx.x; i < n_here * C; i += blockDim.x) dst[i] = s_out[i];
 }
 
 // ------------------------------------------------------------- backward
@@ -79,45 +107,64 @@ __device__ __forceinline__ float seg_sum(float x, int lane, int head) {
   return x;
 }
 
-// One thread per pixel; a wave covers 64 consecutive pixels of the packed
-// buffer, so along one image row.  A triangle meets a row in one run of
-// pixels (it is convex), so after the per-pixel work the wave sums each
-// run's contributions with a segmented reduction and only the last lane of
-// the run issues the global float atomics.
+// Backward sweep over 16x16 pixel tiles of one view per workgroup (256
+// threads; wave w holds rows 4w..4w+3, 16 lanes per row).
+//  1. each lane computes its pixel's fragment gradient from the micro-edges
+//     it belongs to (Sec. 4.2-4.4) and its interpolation adjoint (Omega);
+//  2. lanes sum runs of equal triangle along each 16-pixel row (a triangle
+//     meets a row in one run: it is convex) with a segmented wave reduction;
+//  3. the last lane of each run adds the run's sums into an LDS table keyed
+//     by vertex (a vertex is shared by the runs of several triangles);
+//  4. the workgroup flushes the table with one global float atomic per
+//     (vertex, component).  Vertices that do not fit the table, and
+//     attribute channels beyond kCTab, go straight to global atomics.
+constexpr int kSlots = 512;  // vertex slots per workgroup
+constexpr int kCTab = 8;     // attribute channels reduced in LDS
+constexpr int kNV = 3 + kCTab;
+
+__device__ __forceinline__ int slot_of(int* s_key, int key) {
+  unsigned h = ((unsigned)key * 2654435761u) >> 23;  // 9 bits
+#pragma unroll 1
+  for (int probe = 0; probe < 32; ++probe) {
+    const int s = (int)((h + probe) & (kSlots - 1));
+    const int old = atomicCAS(&s_key[s], -1, key);
+    if (old == -1 || old == key) return s;
+  }
+  return -1;
+}
+
 __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ views, int n_views,
+                                                  const long long* __restrict__ btile_base,
                                                   const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                   const int32_t* __restrict__ tri_id, const float* __restrict__ attr,
                                                   int C_a, int append_z, const float* __restrict__ img,
                                                   const float* __restrict__ g, int C_e, int ld_g, int flags,
-                                                  float* __restrict__ g_attr, float* __restrict__ g_v,
-                                                  long long px_begin, long long total_px) {
-  const long long p = px_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+                                                  float* __restrict__ g_attr, float* __restrict__ g_v) {
+  __shared__ int s_key[kSlots];
+  __shared__ float s_val[kSlots * kNV];
+  for (int i = threadIdx.x; i < kSlots; i += blockDim.x) s_key[i] = -1;
+  for (int i = threadIdx.x; i < kSlots * kNV; i += blockDim.x) s_val[i] = 0.f;
+
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
+  const mer_view vw = views[vi];
+  const long long local_tile = (long long)blockIdx.x - btile_base[vi];
+  const int tiles_x = (vw.W + 15) >> 4;
   const int lane = threadIdx.x & 63;
-  int vi = -1, px = 0, py = -1, t = -1;
-  mer_view vw;
-  vw.v_off = vw.a_off = 0;
-  vw.n_v = vw.n_t = vw.H = vw.W = 0;
-  const int wvi = wave_view(views, n_views, p - lane);
-  if (p < total_px) {
-    vi = wvi;
-    if (vi + 1 < n_views && p >= views[vi + 1].px_off) vi = find_view_px(views, n_views, p);
-    vw = views[vi];
-    const long long local = p - vw.px_off;
-    if (local >= 0 && local < (long long)vw.H * vw.W) {
-      px = (int)(local % vw.W);
-      py = (int)(local / vw.W);
-      t = tri_id[p];
-      if (t >= vw.n_t || t < 0) t = -1;
-    } else {
-      vi = -1;
-    }
+  const int px = (int)(local_tile % tiles_x) * 16 + (lane & 15);
+  const int py = (int)(local_tile / tiles_x) * 16 + (threadIdx.x >> 4);
+  const bool inside = px < vw.W && py < vw.H;
+  const long long p = vw.px_off + (long long)py * vw.W + px;
+  int t = -1;
+  if (inside) {
+    t = tri_id[p];
+    if (t >= vw.n_t || t < 0) t = -1;
   }
   Snap S;
   S.ok = false;
   if (t >= 0) S = snap_id(v, tri, vw, t);
   if (t >= 0 && !S.ok) t = -1;
 
-  // ---- micro-edge term: fragment gradient (r_x, r_y, r_q) of this pixel
+  // ---- micro-edge term: fragment gradient (rx, ry, rq) of this pixel
   float rx = 0.f, ry = 0.f, rq = 0.f;
   // a background pixel is never the top side of a pair, so it receives nothing
   if (t >= 0 && !(flags & MER_SKIP_EDGE)) {
@@ -176,9 +223,9 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
     }
   }
 
-  // ---- runs of equal (view, row, triangle) inside the wave
-  const int t_prev = __shfl_up(t, 1, 64), py_prev = __shfl_up(py, 1, 64), vi_prev = __shfl_up(vi, 1, 64);
-  const bool head_flag = lane == 0 || t != t_prev || py != py_prev || vi != vi_prev;
+  // ---- runs of equal triangle along each 16-pixel row of the wave
+  const int t_prev = __shfl_up(t, 1, 64);
+  const bool head_flag = (lane & 15) == 0 || t != t_prev;
   const unsigned long long F = __ballot(head_flag);
   const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
   const int head = 63 - __clzll((long long)(F & upto));
@@ -198,6 +245,12 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
     gy[k] = pb.beta[k] * ry;
     gz[k] = pb.beta[k] * rq * (-(qk * qk));
   }
+  __syncthreads();  // table cleared
+  int slot[3] = {-1, -1, -1};
+  if (emit) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) slot[k] = slot_of(s_key, S.idx[k]);
+  }
 
   // ---- interpolation adjoint and Omega
   if (!(flags & MER_SKIP_INTERP)) {
@@ -213,7 +266,10 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
         if (t >= 0) G[k] += gc * attr[arow[k] + c];
         if (g_attr) {
           const float s = seg_sum(pb.b[k] * gc, lane, head);
-          if (emit) atomicAdd(g_attr + arow[k] + c, s);
+          if (emit && s != 0.f) {
+            if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], s);
+            else atomicAdd(g_attr + arow[k] + c, s);
+          }
         }
       }
     }
@@ -252,14 +308,31 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   if (g_v) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float sx = seg_sum(gx[k], lane, head);
-      const float sy = seg_sum(gy[k], lane, head);
-      const float sz = seg_sum(gz[k], lane, head);
+      const float sums[3] = {seg_sum(gx[k], lane, head), seg_sum(gy[k], lane, head), seg_sum(gz[k], lane, head)};
       if (emit) {
-        float* gvk = g_v + (vw.v_off + S.idx[k]) * 3;
-        if (sx != 0.f) atomicAdd(gvk + 0, sx);
-        if (sy != 0.f) atomicAdd(gvk + 1, sy);
-        if (sz != 0.f) atomicAdd(gvk + 2, sz);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          if (sums[j] == 0.f) continue;
+          if (slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + j], sums[j]);
+          else atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, sums[j]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- flush: one global atomic per (vertex, component) of this tile
+  const int nv = 3 + min(C_a, kCTab);
+  for (int s = threadIdx.x >> 5; s < kSlots; s += (int)(blockDim.x >> 5)) {
+    const int key = s_key[s];
+    if (key < 0) continue;
+    for (int j = threadIdx.x & 31; j < nv; j += 32) {
+      const float x = s_val[s * kNV + j];
+      if (x == 0.f) continue;
+      if (j < 3) {
+        if (g_v) atomicAdd(g_v + (vw.v_off + key) * 3 + j, x);
+      } else if (g_attr) {
+        atomicAdd(g_attr + (vw.a_off + key) * C_a + (j - 3), x);
       }
     }
   }
@@ -269,17 +342,25 @@ int launch_interpolate(const mer_plan* P, const mer_view* views, const float* at
                        const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
                        hipStream_t st) {
   const long long n = P->total_px - P->px_begin;
-  hipLaunchKernelGGL(k_interp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views, attr, C_a, v,
+  const int C = C_a + append_z;
+  const int bs = C <= 32 ? 256 : 128;  // keeps the LDS staging buffer at or below 32 KB
+  const size_t lds = (size_t)bs * C * sizeof(float);
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), lds, st, views, P->n_views, attr, C_a, v,
                      tri, tri_id, bary, append_z, out, P->px_begin, P->total_px);
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
-                    const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, hipStream_t st) {
-  const long long n = P->total_px - P->px_begin;
-  hipLaunchKernelGGL(k_backward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views, v, tri,
-                     tri_id, attr, C_a, append_z, img, g, C_e, ld_g, flags, g_attr, g_v, P->px_begin, P->total_px);
+                    const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, void* ws,
+                    hipStream_t st) {
+  long long* tab = (long long*)((char*)ws + P->off_bviewtab);
+  // 16x16 tile prefix per view; the rasterizer's status words are left alone
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, 4, 4, tab, tab + (P->n_views + 1),
+                     (long long*)nullptr);
+  hipLaunchKernelGGL(k_backward, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
+                     tab + (P->n_views + 1), v, tri, tri_id, attr, C_a, append_z, img, g, C_e, ld_g, flags, g_attr,
+                     g_v);
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 

@@ -4,14 +4,20 @@
 //
 // Pipeline for one mer_rasterize call over all views:
 //   k_prep      per-view prefix tables (triangles, tiles), clear tile counters
-//   k_setup     one thread per (view, triangle): snap, cull, 64-byte coverage
-//               record, pixel-centre bounding box, count overlapped tiles
+//   k_setup     one thread per (view, triangle): snap, cull; a triangle whose
+//               box of pixel centres is small is rasterized right there
+//               (coverage + depth key + 64-bit atomic max into the per-pixel
+//               key); a larger one gets a 64-byte coverage record, its box,
+//               and counts the tiles it overlaps
 //   k_scan_*    exclusive scan of tile counts -> bin offsets
 //   k_fill      one thread per (view, triangle): write its record index into
 //               every overlapped tile's list
-//   k_raster    one workgroup per tile, one lane per pixel: stage the tile's
-//               records in LDS, exact coverage, binary32 depth key, 64-bit
-//               (1/z, ~id) max; then resolve depth and barycentrics
+//   k_raster    one workgroup per tile, one lane per pixel: start from the
+//               pixel's key, stage the tile's records in LDS, exact coverage,
+//               binary32 depth key, 64-bit (1/z, ~id) max; then resolve the
+//               winner's depth and barycentrics from its vertices
+// The (1/z, ~id) maximum does not depend on the order in which candidates
+// arrive, so both paths and any tile shape give the same index image.
 #include "mer_internal.h"
 
 namespace mer {
@@ -53,12 +59,17 @@ __global__ void __launch_bounds__(1024) k_prep(const mer_view* __restrict__ view
     tri_base[n_views] = s_tri[1023];
     tile_base[n_views] = s_tile[1023];
   }
-  if (tid < 8) status[tid] = 0;
+  if (status && tid < 8) status[tid] = 0;
 }
 
 __global__ void k_zero_i32(int* __restrict__ p, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     p[i] = 0;
+}
+
+__global__ void k_zero_u64(unsigned long long* __restrict__ p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
 }
 
 // ---------------------------------------------------------------- setup
@@ -70,8 +81,9 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
                                                const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                const long long* __restrict__ tri_base,
                                                const long long* __restrict__ tile_base, long long total_tris,
-                                               int tw_log2, int th_log2, Rec* __restrict__ rec,
-                                               BBox* __restrict__ bbox, int* __restrict__ count,
+                                               int tw_log2, int th_log2, int small_px, long long px_begin,
+                                               Rec* __restrict__ rec, BBox* __restrict__ bbox,
+                                               int* __restrict__ count, unsigned long long* __restrict__ key,
                                                long long* __restrict__ status) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool culled = false;
@@ -84,7 +96,7 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
     if (!s.ok) {
       culled = true;
     } else {
-      rec[g] = make_rec(s);
+      const Rec R = make_rec(s);
       int xmin = min(s.X[0], min(s.X[1], s.X[2])), xmax = max(s.X[0], max(s.X[1], s.X[2]));
       int ymin = min(s.Y[0], min(s.Y[1], s.Y[2])), ymax = max(s.Y[0], max(s.Y[1], s.Y[2]));
       // pixel centres 256 p + 128 within [min, max]: p in [ceil((min-128)/256), floor((max-128)/256)]
@@ -94,7 +106,20 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
       pya = max(pya, 0);
       pxb = min(pxb, vw.W - 1);
       pyb = min(pyb, vw.H - 1);
-      if (pxa <= pxb && pya <= pyb) {
+      if (pxa <= pxb && pya <= pyb && (pxb - pxa + 1) * (pyb - pya + 1) <= small_px) {
+        // small triangle: rasterize its few pixel centres here
+        unsigned long long* kv = key + (vw.px_off - px_begin);
+        for (int y = pya; y <= pyb; ++y)
+          for (int x = pxa; x <= pxb; ++x) {
+            long long E[3];
+            edge_eval(R, x, y, E);
+            if (!covered(E)) continue;
+            float e[3], d;
+            edge_values(R, E, e, d);
+            atomicMax(kv + (long long)y * vw.W + x, vis_key(depth_key(R, e, d), (int)t));
+          }
+      } else if (pxa <= pxb && pya <= pyb) {
+        rec[g] = R;
         bb.x0 = (short)pxa;
         bb.x1 = (short)pxb;
         bb.y0 = (short)pya;
@@ -224,14 +249,16 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    const long long* __restrict__ tile_base,
                                                    const Rec* __restrict__ rec, const BBox* __restrict__ bbox,
                                                    const int* __restrict__ offs, const int* __restrict__ bins,
-                                                   long long bin_cap, int32_t* __restrict__ tri_id,
+                                                   long long bin_cap, const unsigned long long* __restrict__ key,
+                                                   long long px_begin, const float* __restrict__ v,
+                                                   const int32_t* __restrict__ tri, int32_t* __restrict__ tri_id,
                                                    float* __restrict__ depth, float* __restrict__ bary,
                                                    long long* __restrict__ status) {
   constexpr int NT = TW * TH;
   __shared__ Rec s_rec[NT];
   __shared__ int s_tid[NT];
   const long long g = blockIdx.x;
-  const int vi = find_bucket(tile_base, n_views, g);
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
   const mer_view vw = views[vi];
   const long long local = g - tile_base[vi];
   const int tiles_x = (vw.W + TW - 1) / TW;
@@ -247,7 +274,8 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const long long n_items = overflow ? (tri_base[vi + 1] - tb) : (end - start);
   if (overflow && threadIdx.x == 0) atomicAdd((unsigned long long*)status, 1ull);
 
-  unsigned long long best = 0ull;
+  const long long p = vw.px_off + (long long)py * vw.W + px;
+  unsigned long long best = inside ? key[p - px_begin] : 0ull;
   for (long long c0 = 0; c0 < n_items; c0 += NT) {
     const int n = (int)min((long long)NT, n_items - c0);
     if (threadIdx.x < n) {
@@ -284,24 +312,15 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
     __syncthreads();
   }
   if (!inside) return;
-  const long long p = vw.px_off + (long long)py * vw.W + px;
   const int t = key_tri(best);
   tri_id[p] = t;
   if (depth) depth[p] = t >= 0 ? 1.0f / key_q(best) : 0.0f;
   if (bary) {
     float b0 = 0.f, b1 = 0.f;
     if (t >= 0) {
-      const Rec R = rec[tb + t];
-      long long E[3];
-      edge_eval(R, px, py, E);
-      float e[3], d;
-      edge_values(R, E, e, d);
-      float w[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) w[k] = (e[k] / d) * R.q[k];
-      const float W = (w[0] + w[1]) + w[2];
-      b0 = w[0] / W;
-      b1 = w[1] / W;
+      const PixBary pb = pixel_bary(snap_triangle(v, vw, tri + (vw.t_off + t) * 3), px, py);
+      b0 = pb.b[0];
+      b1 = pb.b[1];
     }
     bary[2 * p] = b0;
     bary[2 * p + 1] = b1;
@@ -322,14 +341,18 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   int* part = (int*)(w + P->off_part);
   int* bins = (int*)(w + P->off_bins);
   long long* status = (long long*)(w + P->off_status);
+  unsigned long long* key = (unsigned long long*)(w + P->off_key);
+  const long long npx = P->total_px - P->px_begin;
   const int twl = __builtin_ctz(P->tile_w), thl = __builtin_ctz(P->tile_h);
 
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, twl, thl, tri_base, tile_base, status);
   const long long nt = P->total_tiles;
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)min((nt + 255) / 256, 4096ll)), dim3(256), 0, st, count, nt);
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)min((npx + 255) / 256, 8192ll)), dim3(256), 0, st, key, npx);
   if (P->total_tris > 0) {
     hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
-                       v, tri, tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, status);
+                       v, tri, tri_base, tile_base, P->total_tris, twl, thl, P->small_px, P->px_begin, rec, bbox, count,
+                       key, status);
   }
   hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(256), 0, st, part, P->n_part);
@@ -340,7 +363,7 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   }
 #define MER_RASTER(TW, TH)                                                                                       \
   hipLaunchKernelGGL((k_raster<TW, TH>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views, P->n_views, tri_base, \
-                     tile_base, rec, bbox, offs, bins, P->bin_cap, tri_id, depth, bary, status)
+                     tile_base, rec, bbox, offs, bins, P->bin_cap, key, P->px_begin, v, tri, tri_id, depth, bary, status)
   if (P->tile_w == 8 && P->tile_h == 8) MER_RASTER(8, 8);
   else if (P->tile_w == 16 && P->tile_h == 16) MER_RASTER(16, 16);
   else if (P->tile_w == 32 && P->tile_h == 8) MER_RASTER(32, 8);

@@ -30,17 +30,19 @@ class View(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("bin_cap", ctypes.c_int64)]
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("bin_cap", ctypes.c_int64),
+                ("small_px", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
     _fields_ = [("n_views", ctypes.c_int32), ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("total_tris", ctypes.c_int64), ("total_tiles", ctypes.c_int64),
+                ("small_px", ctypes.c_int32), ("total_tris", ctypes.c_int64), ("total_tiles", ctypes.c_int64),
                 ("total_px", ctypes.c_int64), ("bin_cap", ctypes.c_int64), ("px_begin", ctypes.c_int64),
                 ("ws_bytes", ctypes.c_int64),
                 ("off_viewtab", ctypes.c_int64), ("off_rec", ctypes.c_int64), ("off_bbox", ctypes.c_int64),
                 ("off_count", ctypes.c_int64), ("off_offs", ctypes.c_int64), ("off_part", ctypes.c_int64),
-                ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("n_part", ctypes.c_int64)]
+                ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("off_key", ctypes.c_int64),
+                ("n_part", ctypes.c_int64), ("total_btiles", ctypes.c_int64), ("off_bviewtab", ctypes.c_int64)]
 
 
 class MerError(RuntimeError):
@@ -61,9 +63,9 @@ def lib():
         L.mer_plan_init.argtypes = [ctypes.POINTER(View), i, ctypes.POINTER(Tuning), ctypes.POINTER(Plan)]
         L.mer_rasterize.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, P]
         L.mer_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, P, i, P, P]
-        L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P]
-        L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P]
-        L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P]
+        L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P, P]
+        L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P, P]
+        L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
         L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
         L.mer_strerror.argtypes = [i]
         L.mer_strerror.restype = ctypes.c_char_p
@@ -89,9 +91,9 @@ def views_struct(views_i64: np.ndarray):
     return arr
 
 
-def plan_init(views_i64, tile=(8, 8), bin_cap=0) -> Plan:
+def plan_init(views_i64, tile=(8, 8), bin_cap=0, small_px=0) -> Plan:
     vs = views_struct(views_i64)
-    tun = Tuning(int(tile[0]), int(tile[1]), int(bin_cap))
+    tun = Tuning(int(tile[0]), int(tile[1]), int(bin_cap), int(small_px), 0)
     P = Plan()
     _check(lib().mer_plan_init(vs, len(vs), ctypes.byref(tun), ctypes.byref(P)))
     return P
@@ -123,10 +125,10 @@ class Context:
     current torch stream.
     """
 
-    def __init__(self, views_i64, device="cuda", tile=(8, 8), bin_cap=0):
+    def __init__(self, views_i64, device="cuda", tile=(8, 8), bin_cap=0, small_px=0):
         import torch
         self.views_i64 = np.asarray(views_i64, np.int64)
-        self.plan = plan_init(self.views_i64, tile, bin_cap)
+        self.plan = plan_init(self.views_i64, tile, bin_cap, small_px)
         raw = bytes(views_struct(self.views_i64))
         self.views_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
         self.ws = torch.empty(int(self.plan.ws_bytes), dtype=torch.uint8, device=device)
@@ -205,7 +207,8 @@ class Context:
         self._px(img, "img")
         self._px(g_img, "g_img", int(img.shape[1]))
         _check(lib().mer_edge_grad(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
-                                   _ptr(img), _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_v), _stream()))
+                                   _ptr(img), _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_v), _ptr(self.ws),
+                                   _stream()))
 
     def interpolate_bwd(self, attr, v, tri, tri_id, g_out, g_attr=None, g_v=None, append_z=False):
         import torch
@@ -223,7 +226,8 @@ class Context:
             self._rows(g_v, self.need_v, "g_v", 3)
         _check(lib().mer_interpolate_bwd(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(attr),
                                          int(attr.shape[1]), _ptr(v), _ptr(tri), _ptr(tri_id), int(bool(append_z)),
-                                         _ptr(g_out), int(g_out.shape[1]), _ptr(g_attr), _ptr(g_v), _stream()))
+                                         _ptr(g_out), int(g_out.shape[1]), _ptr(g_attr), _ptr(g_v), _ptr(self.ws),
+                                         _stream()))
 
     def backward(self, v, tri, tri_id, attr, img, g_img, g_attr, g_v, append_z=False, flags=0):
         import torch
@@ -244,7 +248,7 @@ class Context:
         _check(lib().mer_backward_fused(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri),
                                         _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
                                         _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_attr), _ptr(g_v),
-                                        _stream()))
+                                        _ptr(self.ws), _stream()))
 
     def status(self):
         out = (ctypes.c_int64 * 4)()

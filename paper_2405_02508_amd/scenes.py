@@ -188,6 +188,7 @@ class Scene:
     mask_channel: bool       # coverage mask appended to the edge-gradient image
     v_target: np.ndarray | None = None   # perturbed screen vertices for an L2 target
     recompute: bool = False  # workload asks for barycentrics recomputed in backward
+    meta: dict = dataclasses.field(default_factory=dict)
 
     @property
     def n_views(self):
@@ -336,8 +337,9 @@ def make_config(k: int, small: bool = False) -> Scene:
             vt = V + rng.normal(0, 0.01, size=V.shape)
             per.append((project(V, cam), F, s, s, Hd, Wd))
             tgt.append(project(vt, cam))
-        return _pack(f"batched-{n_scenes}-scenes", per, attrs, False, False,
-                     target_per_view=tgt)
+        sc = _pack(f"batched-{n_scenes}-scenes", per, attrs, False, False, target_per_view=tgt)
+        sc.meta["intersecting"] = [int(i) for i in np.nonzero(inter)[0]]
+        return sc
     if k == 5:
         nu = 32 if small else 224
         n_cam = 2 if small else 16

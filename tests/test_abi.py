@@ -68,9 +68,11 @@ def test_plan_totals_and_layout(L):
     P = mer.plan_init(V, (8, 8))
     assert P.total_tris == 40 and P.total_px == 17 * 33 + 64
     assert P.total_tiles == 3 * 5 + 1
-    offs = [P.off_viewtab, P.off_rec, P.off_bbox, P.off_count, P.off_offs, P.off_part, P.off_bins, P.off_status]
+    offs = [P.off_viewtab, P.off_rec, P.off_bbox, P.off_count, P.off_offs, P.off_part, P.off_bins, P.off_status,
+            P.off_key]
     assert offs == sorted(offs) and all(o % 256 == 0 for o in offs) and P.ws_bytes > offs[-1]
-    assert P.bin_cap > 0
+    assert P.bin_cap > 0 and P.small_px == 16
+    assert P.ws_bytes - P.off_key >= 8 * P.total_px
     P2 = mer.plan_init(V, (16, 16), bin_cap=5)
     assert P2.bin_cap == 5 and P2.total_tiles == 2 * 3 + 1
 

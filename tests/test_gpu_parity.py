@@ -30,6 +30,16 @@ def test_parity_small_configs(k, tile):
     say(f"[parity] config {k} ok {errs}")
 
 
+@pytest.mark.parametrize("k", [1, 2, 4, 5])
+@pytest.mark.parametrize("small_px", [-1, 4096])
+def test_parity_small_triangle_limit(k, small_px):
+    """Every triangle binned (-1) or nearly every triangle rasterized by its
+    set-up thread (4096): same index image, same gradients."""
+    s, g, ref = case(k)
+    say(f"[parity] config {k} small_px {small_px}")
+    compare(run_gpu(s, g, small_px=small_px), ref)
+
+
 @pytest.mark.parametrize("k", [3, 4])
 def test_parity_per_view_launches(k):
     s, g, ref = case(k)
