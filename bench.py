@@ -41,7 +41,7 @@ def log(*a):
 class Step:
     """Device buffers and the call sequence of one step for a set of views."""
 
-    def __init__(self, scene, groups, tile, store_bary, dev):
+    def __init__(self, scene, groups, tile, store_bary, dev, small_px=0, bin_cap=0):
         import torch
 
         from paper_2405_02508_amd import mer
@@ -60,7 +60,8 @@ class Step:
         self.g = torch.empty(n, s.C_e, dtype=torch.float32, device=dev)
         self.g_v = torch.zeros_like(self.v)
         self.g_attr = torch.zeros_like(self.attr)
-        self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile) for grp in groups]
+        self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile, small_px=small_px,
+                                 bin_cap=bin_cap if len(groups) == 1 else 0) for grp in groups]
         # L2 target image rendered once from perturbed vertices (outside the timed region)
         self.target = torch.zeros(n, s.C_e, dtype=torch.float32, device=dev)
         if s.v_target is not None:
@@ -72,6 +73,7 @@ class Step:
             self.target.copy_(self.img)
         else:
             self.target.copy_(torch.rand(n, s.C_e, generator=torch.Generator(device=dev).manual_seed(7), device=dev))
+        self.neg2t = (-2.0 * self.target).contiguous()  # L = sum (I - T)^2  ->  g = 2 I - 2 T in one pass
 
     def _assemble(self):
         if self.img is not self.interp:
@@ -88,8 +90,7 @@ class Step:
 
     def loss_grad(self):
         import torch
-        torch.sub(self.img, self.target, out=self.g)
-        self.g.mul_(2.0)
+        torch.add(self.neg2t, self.img, alpha=2.0, out=self.g)
 
     def backward(self):
         self.g_v.zero_()
@@ -120,28 +121,30 @@ def kernel_times(st, iters, stream):
     """Average duration of each library call on its stream, HIP events."""
     import torch
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    names = ("rasterize", "interpolate", "backward")
+    names = ("rasterize", "interpolate", "loss", "backward")
     acc = {k: 0.0 for k in names}
     for _ in range(iters):
-        marks = [ev() for _ in range(4)]
+        marks = [ev() for _ in range(6)]
         marks[0].record(stream)
         for c in st.ctxs:
             c.rasterize(st.v, st.tri, st.tid, st.depth, st.bary)
         marks[1].record(stream)
         for c in st.ctxs:
             c.interpolate(st.attr, st.v, st.tri, st.tid, st.interp, bary=st.bary, append_z=st.s.append_z)
+        marks[2].record(stream)
         st._assemble()
         st.loss_grad()
         st.g_v.zero_()
         st.g_attr.zero_()
-        marks[2].record(stream)
+        marks[3].record(stream)
         for c in st.ctxs:
             c.backward(st.v, st.tri, st.tid, st.attr, st.img, st.g, st.g_attr, st.g_v, append_z=st.s.append_z)
-        marks[3].record(stream)
+        marks[4].record(stream)
         torch.cuda.synchronize()
         acc["rasterize"] += marks[0].elapsed_time(marks[1])
         acc["interpolate"] += marks[1].elapsed_time(marks[2])
-        acc["backward"] += marks[2].elapsed_time(marks[3])
+        acc["loss"] += marks[2].elapsed_time(marks[3])
+        acc["backward"] += marks[3].elapsed_time(marks[4])
     return {k: acc[k] / iters for k in names}
 
 
@@ -186,7 +189,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=4, choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="8x8")
+    ap.add_argument("--tile", default="auto", help="WxH, or 'auto' for the autotuner's choice")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
@@ -200,15 +203,24 @@ def main():
     from paper_2405_02508_amd import mer, scenes
     mer.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
-    tile = tuple(int(x) for x in args.tile.split("x"))
     t0 = time.perf_counter()
     s = scenes.make_config(args.workload)
     log(f"[bench] workload {args.workload} {s.name}: {s.n_views} views, {s.n_px} px, "
         f"{int(s.views[:, 5].sum())} view-tris, scene built in {time.perf_counter() - t0:.1f}s")
     stream = torch.cuda.current_stream()
+    if args.tile == "auto":
+        from paper_2405_02508_amd import autotune
+        t0 = time.perf_counter()
+        tu = autotune.tune(s.views, torch.from_numpy(s.v).to(dev), torch.from_numpy(s.tri).to(dev), log=log)
+        tuning = {"tile": list(tu["tile"]), "small_px": tu["small_px"], "bin_cap": tu["bin_cap"],
+                  "source": "autotuner (cached)" if tu.get("cached") else "autotuner"}
+        log(f"[bench] autotune {time.perf_counter() - t0:.1f}s -> {tuning}")
+    else:
+        tuning = {"tile": [int(x) for x in args.tile.split("x")], "small_px": 0, "bin_cap": 0, "source": "flag"}
+    tile = tuple(tuning["tile"])
 
     # ---- batched: every view in one plan, captured in a HIP graph
-    st = Step(s, [list(range(s.n_views))], tile, not s.recompute, dev)
+    st = Step(s, [list(range(s.n_views))], tile, not s.recompute, dev, tuning["small_px"], tuning["bin_cap"])
     for _ in range(args.warmup):
         st.run()
     torch.cuda.synchronize()
@@ -241,7 +253,7 @@ def main():
     used_graph = graph is not None
     if not args.no_per_view and s.n_views > 1:
         graph = None
-        st_pv = Step(s, [[i] for i in range(s.n_views)], tile, not s.recompute, dev)
+        st_pv = Step(s, [[i] for i in range(s.n_views)], tile, not s.recompute, dev, tuning["small_px"])
         for _ in range(max(1, args.warmup)):
             st_pv.run()
         ms_pv = time_region(st_pv.run, max(2, args.steps // 4), stream)
@@ -249,7 +261,7 @@ def main():
         log(f"[bench] per-view eager: {ms_pv:.3f} ms/step")
         del st_pv
 
-    dom = max(kt, key=kt.get)
+    dom = max((k for k in kt if k != "loss"), key=kt.get)
     ab = algorithmic_bytes(s, dom)
     achieved = ab / (kt[dom] * 1e-3) / 1e9
     out = {
@@ -267,7 +279,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"config {args.workload}: {WORKLOADS[args.workload]}", "scene": s.name,
                    "views": s.n_views, "pixels": s.n_px, "view_triangles": int(s.views[:, 5].sum()),
-                   "tile": args.tile, "graph": used_graph, "barycentrics": "recomputed" if s.recompute else "stored"},
+                   "tuning": tuning, "graph": used_graph, "barycentrics": "recomputed" if s.recompute else "stored"},
         "per_view": pv,
         "per_call_ms": {k: round(v, 4) for k, v in kt.items()},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,

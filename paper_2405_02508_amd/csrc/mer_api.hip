@@ -57,7 +57,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   P->total_tiles = tiles;
   P->total_btiles = btiles;
   P->total_px = px_end;
-  int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 4 * tris + 16 * tiles + 4096;
+  int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 16 * tris + 16 * tiles + 4096;
   if (cap > INT_MAX) cap = INT_MAX;
   P->bin_cap = cap;
   P->small_px = (tun && tun->small_px != 0) ? (tun->small_px < 0 ? 0 : tun->small_px) : 16;

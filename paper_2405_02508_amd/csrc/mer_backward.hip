@@ -27,8 +27,10 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
   float b0 = 0.f, b1 = 0.f, b2 = 0.f;
   int idx[3] = {0, 0, 0};
   mer_view vw;
+  const int wvi = wave_view(views, n_views, p - (threadIdx.x & 63));
   if (p < total_px) {
-    const int vi = find_view_px(views, n_views, p);
+    int vi = wvi;
+    if (vi + 1 < n_views && p >= views[vi + 1].px_off) vi = find_view_px(views, n_views, p);
     vw = views[vi];
     const long long local = p - vw.px_off;
     valid = local >= 0 && local < (long long)vw.H * vw.W;
@@ -97,13 +99,22 @@ __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, cons
   return snap_triangle(v, vw, tri + (vw.t_off + t) * 3);
 }
 
-// Segmented inclusive sum over lanes [head, lane] of a wave64.
-__device__ __forceinline__ float seg_sum(float x, int lane, int head) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const float y = __shfl_up(x, off, 64);
-    if (lane - off >= head) x += y;
-  }
+// Segmented inclusive sum over lanes [hir, lir] of one 16-lane row of a
+// wave, with DPP row shifts (row_shr:1, 2, 4, 8).
+template <int CTRL>
+__device__ __forceinline__ float dpp_row_shr(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float seg_sum(float x, int lir, int hir) {
+  float y;
+  y = dpp_row_shr<0x111>(x);
+  if (lir - 1 >= hir) x += y;
+  y = dpp_row_shr<0x112>(x);
+  if (lir - 2 >= hir) x += y;
+  y = dpp_row_shr<0x114>(x);
+  if (lir - 4 >= hir) x += y;
+  y = dpp_row_shr<0x118>(x);
+  if (lir - 8 >= hir) x += y;
   return x;
 }
 
@@ -197,8 +208,14 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
         continue;
       }
       const Snap Sn = snap_id(v, tri, vw, tn);
-      const Snap& SA = selfA ? S : Sn;
-      const Snap& SB = selfA ? Sn : S;
+      Snap SA, SB;  // by value: a conditional reference would force the structs to scratch
+      if (selfA) {
+        SA = S;
+        SB = Sn;
+      } else {
+        SA = Sn;
+        SB = S;
+      }
       const int ax_ = selfA ? px : nx, ay_ = selfA ? py : ny;
       const int bx_ = selfA ? nx : px, by_ = selfA ? ny : py;
       const bool cA = contains(SB, ax_, ay_);  // B's triangle holds A's centre
@@ -231,12 +248,13 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   const int head = 63 - __clzll((long long)(F & upto));
   const bool tail = lane == 63 || ((F >> (lane + 1)) & 1ull);
   const bool emit = tail && t >= 0;
+  const int lir = lane & 15, hir = head & 15;  // runs never cross a 16-lane row
 
   PixBary pb;
   pb.beta[0] = pb.beta[1] = pb.beta[2] = 0.f;
   pb.b[0] = pb.b[1] = pb.b[2] = 0.f;
   pb.Wq = 1.f;
-  if (t >= 0) pb = pixel_bary(S, px, py);
+  if (t >= 0) pb = pixel_bary_grad(S, px, py);
   float gx[3], gy[3], gz[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -265,7 +283,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
       for (int k = 0; k < 3; ++k) {
         if (t >= 0) G[k] += gc * attr[arow[k] + c];
         if (g_attr) {
-          const float s = seg_sum(pb.b[k] * gc, lane, head);
+          const float s = seg_sum(pb.b[k] * gc, lir, hir);
           if (emit && s != 0.f) {
             if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], s);
             else atomicAdd(g_attr + arow[k] + c, s);
@@ -282,15 +300,16 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
         }
       }
       const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
+      const float iW = __builtin_amdgcn_rcpf(pb.Wq);
       float dbeta[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float dw = (G[k] - Gb) / pb.Wq;
+        const float dw = (G[k] - Gb) * iW;
         dbeta[k] = dw * S.q[k];
         gz[k] += (dw * pb.beta[k]) * (-(S.q[k] * S.q[k]));
       }
       // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
-      const float invD = 256.0f / (float)S.D;
+      const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
       float sx = 0.f, sy = 0.f;
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -308,7 +327,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   if (g_v) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float sums[3] = {seg_sum(gx[k], lane, head), seg_sum(gy[k], lane, head), seg_sum(gz[k], lane, head)};
+      const float sums[3] = {seg_sum(gx[k], lir, hir), seg_sum(gy[k], lir, hir), seg_sum(gz[k], lir, hir)};
       if (emit) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {

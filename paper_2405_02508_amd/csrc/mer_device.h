@@ -96,12 +96,24 @@ __device__ __forceinline__ Rec make_rec(const Snap& s) {
 
 // Biased edge functions at pixel (px, py).
 __device__ __forceinline__ void edge_eval(const Rec& r, int px, int py, long long E[3]) {
-  const long long PX = (long long)px * 256, PY = (long long)py * 256;
+  const int PX = px * 256, PY = py * 256;  // |.| < 2^23: both factors are 32-bit
 #pragma unroll
-  for (int k = 0; k < 3; ++k) E[k] = (long long)r.A[k] * PX + (long long)r.B[k] * PY + r.C[k];
+  for (int k = 0; k < 3; ++k) E[k] = (long long)r.A[k] * (long long)PX + (long long)r.B[k] * (long long)PY + r.C[k];
 }
 
 __device__ __forceinline__ bool covered(const long long E[3]) { return E[0] > 0 && E[1] > 0 && E[2] > 0; }
+
+// Can any pixel centre in [x0, x1] x [y0, y1] be covered?  Each edge function
+// is linear, so its maximum over the box of centres sits at the corner its
+// inward normal points to; if one edge is <= 0 there, no centre is covered.
+__device__ __forceinline__ bool box_may_cover(const Rec& r, int x0, int y0, int x1, int y1) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int X = (r.A[k] > 0 ? x1 : x0) * 256, Y = (r.B[k] > 0 ? y1 : y0) * 256;
+    if ((long long)r.A[k] * (long long)X + (long long)r.B[k] * (long long)Y + r.C[k] <= 0) return false;
+  }
+  return true;
+}
 
 // Exact unbiased edge values as binary32, and d = (float)(|D|).
 __device__ __forceinline__ void edge_values(const Rec& r, const long long E[3], float e[3], float& d) {
@@ -132,13 +144,41 @@ __device__ __forceinline__ int key_tri(unsigned long long k) {
 }
 __device__ __forceinline__ float key_q(unsigned long long k) { return __uint_as_float((unsigned)(k >> 32)); }
 
+// Exact sign(D) * orient(v_{k+1}, v_{k+2}, centre of (px, py)) straight from
+// the snapped vertices: every factor is a 32-bit integer.
+__device__ __forceinline__ void edge_at(const Snap& s, int px, int py, long long E[3]) {
+  const int Px = px * 256 + 128, Py = py * 256 + 128;
+  const bool neg = s.D < 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const long long e = (long long)(s.X[b] - s.X[a]) * (long long)(Py - s.Y[a]) -
+                        (long long)(s.Y[b] - s.Y[a]) * (long long)(Px - s.X[a]);
+    E[k] = neg ? -e : e;
+  }
+}
+
+// Coverage rule on exact edge values: E_k > 0, or E_k == 0 on a top/left edge.
+__device__ __forceinline__ bool covered_at(const Snap& s, const long long E[3]) {
+  const bool neg = s.D < 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (E[k] > 0) continue;
+    if (E[k] < 0) return false;
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const int A = neg ? (s.Y[b] - s.Y[a]) : -(s.Y[b] - s.Y[a]);  // inward normal, x
+    const int B = neg ? -(s.X[b] - s.X[a]) : (s.X[b] - s.X[a]);  // inward normal, y
+    if (!(A > 0 || (A == 0 && B > 0))) return false;
+  }
+  return true;
+}
+
 // Is pixel (px, py)'s centre inside snapped triangle s by the coverage rule?
 __device__ __forceinline__ bool contains(const Snap& s, int px, int py) {
   if (!s.ok) return false;
-  Rec r = make_rec(s);
   long long E[3];
-  edge_eval(r, px, py, E);
-  return covered(E);
+  edge_at(s, px, py, E);
+  return covered_at(s, E);
 }
 
 // Screen barycentrics (exact edge values / D), perspective-correct b, W = sum e_k q_k / d.
@@ -149,11 +189,13 @@ struct PixBary {
 };
 
 __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
-  Rec r = make_rec(s);
   long long E[3];
-  edge_eval(r, px, py, E);
-  float e[3], d;
-  edge_values(r, E, e, d);
+  edge_at(s, px, py, E);
+  float e[3];
+  e[0] = (float)E[0];
+  e[1] = (float)E[1];
+  e[2] = (float)E[2];
+  const float d = (float)(E[0] + E[1] + E[2]);
   PixBary o;
   float w[3];
 #pragma unroll
@@ -165,6 +207,28 @@ __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
   o.b[0] = w[0] / W;
   o.b[1] = w[1] / W;
   o.b[2] = (1.0f - o.b[0]) - o.b[1];
+  o.Wq = W;
+  return o;
+}
+
+// Barycentrics for gradients only: same quantities as pixel_bary, with
+// reciprocals in place of correctly rounded divisions.
+__device__ __forceinline__ PixBary pixel_bary_grad(const Snap& s, int px, int py) {
+  long long E[3];
+  edge_at(s, px, py, E);
+  const float id = __builtin_amdgcn_rcpf((float)(E[0] + E[1] + E[2]));
+  PixBary o;
+  float w[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    o.beta[k] = (float)E[k] * id;
+    w[k] = o.beta[k] * s.q[k];
+  }
+  const float W = (w[0] + w[1]) + w[2];
+  const float iW = __builtin_amdgcn_rcpf(W);
+  o.b[0] = w[0] * iW;
+  o.b[1] = w[1] * iW;
+  o.b[2] = w[2] * iW;
   o.Wq = W;
   return o;
 }
@@ -208,6 +272,18 @@ __device__ __forceinline__ int find_view_px(const mer_view* views, int n, long l
     else hi = mid - 1;
   }
   return lo;
+}
+
+// Bucket of g (see find_bucket), searched once per wave with a wave-uniform
+// index (scalar loads) and per lane only where the wave crosses a bucket end.
+template <typename T>
+__device__ __forceinline__ int wave_bucket(const T* base, int n, long long g) {
+  const long long g0 = g - (threadIdx.x & 63);
+  const long long u = ((long long)__builtin_amdgcn_readfirstlane((int)(g0 >> 32)) << 32) |
+                      (unsigned)__builtin_amdgcn_readfirstlane((int)(g0 & 0xffffffff));
+  int b = __builtin_amdgcn_readfirstlane(find_bucket(base, n, u));
+  if (b + 1 < n && g >= (long long)base[b + 1]) b = find_bucket(base, n, g);
+  return b;
 }
 
 // View of the wave's first pixel, searched with a wave-uniform index so the

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool culled = false;
   if (g < total_tris) {
-    const int vi = find_bucket(tri_base, n_views, g);
+    const int vi = wave_bucket(tri_base, n_views, g);
     const mer_view vw = views[vi];
     const long long t = g - tri_base[vi];
     const Snap s = snap_triangle(v, vw, tri + (vw.t_off + t) * 3);
@@ -127,8 +127,11 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
         const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
         const long long base = tile_base[vi];
         for (int ty = pya >> th_log2; ty <= (pyb >> th_log2); ++ty)
-          for (int tx = pxa >> tw_log2; tx <= (pxb >> tw_log2); ++tx)
-            atomicAdd(count + base + (long long)ty * tiles_x + tx, 1);
+          for (int tx = pxa >> tw_log2; tx <= (pxb >> tw_log2); ++tx) {
+            const int bx0 = max(tx << tw_log2, pxa), bx1 = min(((tx + 1) << tw_log2) - 1, pxb);
+            const int by0 = max(ty << th_log2, pya), by1 = min(((ty + 1) << th_log2) - 1, pyb);
+            if (box_may_cover(R, bx0, by0, bx1, by1)) atomicAdd(count + base + (long long)ty * tiles_x + tx, 1);
+          }
       }
     }
     bbox[g] = bb;
@@ -222,19 +225,24 @@ __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ coun
 __global__ void __launch_bounds__(256) k_fill(const mer_view* __restrict__ views, int n_views,
                                               const long long* __restrict__ tri_base,
                                               const long long* __restrict__ tile_base, long long total_tris,
-                                              int tw_log2, int th_log2, const BBox* __restrict__ bbox,
+                                              int tw_log2, int th_log2, const Rec* __restrict__ rec,
+                                              const BBox* __restrict__ bbox,
                                               int* __restrict__ count, const int* __restrict__ offs,
                                               long long bin_cap, int* __restrict__ bins) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total_tris) return;
   const BBox bb = bbox[g];
   if (bb.x0 > bb.x1) return;
-  const int vi = find_bucket(tri_base, n_views, g);
+  const int vi = wave_bucket(tri_base, n_views, g);
   const mer_view vw = views[vi];
   const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
   const long long base = tile_base[vi];
+  const Rec R = rec[g];
   for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
     for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx) {
+      const int bx0 = max(tx << tw_log2, (int)bb.x0), bx1 = min(((tx + 1) << tw_log2) - 1, (int)bb.x1);
+      const int by0 = max(ty << th_log2, (int)bb.y0), by1 = min(((ty + 1) << th_log2) - 1, (int)bb.y1);
+      if (!box_may_cover(R, bx0, by0, bx1, by1)) continue;  // same test as the count pass
       const long long tile = base + (long long)ty * tiles_x + tx;
       const int slot = atomicSub(count + tile, 1) - 1;
       const long long pos = (long long)offs[tile] + slot;
@@ -359,7 +367,7 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part, offs, status);
   if (P->total_tris > 0) {
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
-                       tri_base, tile_base, P->total_tris, twl, thl, bbox, count, offs, P->bin_cap, bins);
+                       tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, offs, P->bin_cap, bins);
   }
 #define MER_RASTER(TW, TH)                                                                                       \
   hipLaunchKernelGGL((k_raster<TW, TH>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views, P->n_views, tri_base, \
