@@ -95,8 +95,9 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
 }
 
 // ------------------------------------------------------------- backward
+template <bool EXACT_Q>
 __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, const mer_view& vw, int t) {
-  return snap_triangle(v, vw, tri + (vw.t_off + t) * 3);
+  return snap_triangle<EXACT_Q>(v, vw, tri + (vw.t_off + t) * 3);
 }
 
 // Segmented inclusive sum over lanes [hir, lir] of one 16-lane row of a
@@ -105,16 +106,20 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_row_shr(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float seg_sum(float x, int lir, int hir) {
-  float y;
-  y = dpp_row_shr<0x111>(x);
-  if (lir - 1 >= hir) x += y;
-  y = dpp_row_shr<0x112>(x);
-  if (lir - 2 >= hir) x += y;
-  y = dpp_row_shr<0x114>(x);
-  if (lir - 4 >= hir) x += y;
-  y = dpp_row_shr<0x118>(x);
-  if (lir - 8 >= hir) x += y;
+// m[i] is 1 where the lane 2^i places to the left is in the same run, else 0
+// (so the fused multiply-add below adds either the neighbour or exactly 0).
+struct RunMask {
+  float m1, m2, m4, m8;
+};
+__device__ __forceinline__ RunMask run_mask(int lir, int hir) {
+  return {lir - 1 >= hir ? 1.f : 0.f, lir - 2 >= hir ? 1.f : 0.f, lir - 4 >= hir ? 1.f : 0.f,
+          lir - 8 >= hir ? 1.f : 0.f};
+}
+__device__ __forceinline__ float seg_sum(float x, const RunMask& m) {
+  x = __builtin_fmaf(dpp_row_shr<0x111>(x), m.m1, x);
+  x = __builtin_fmaf(dpp_row_shr<0x112>(x), m.m2, x);
+  x = __builtin_fmaf(dpp_row_shr<0x114>(x), m.m4, x);
+  x = __builtin_fmaf(dpp_row_shr<0x118>(x), m.m8, x);
   return x;
 }
 
@@ -133,13 +138,21 @@ constexpr int kSlots = 512;  // vertex slots per workgroup
 constexpr int kCTab = 8;     // attribute channels reduced in LDS
 constexpr int kNV = 3 + kCTab;
 
-__device__ __forceinline__ int slot_of(int* s_key, int key) {
+// Find or claim the slot of vertex `key`; a new slot has its values zeroed
+// and is appended to the occupied list.  -1 when the probe limit is hit.
+__device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, int* s_nocc, int key) {
   unsigned h = ((unsigned)key * 2654435761u) >> 23;  // 9 bits
 #pragma unroll 1
   for (int probe = 0; probe < 32; ++probe) {
     const int s = (int)((h + probe) & (kSlots - 1));
     const int old = atomicCAS(&s_key[s], -1, key);
-    if (old == -1 || old == key) return s;
+    if (old == -1) {
+#pragma unroll
+      for (int j = 0; j < kNV; ++j) s_val[s * kNV + j] = 0.f;
+      s_list[atomicAdd(s_nocc, 1)] = s;
+      return s;
+    }
+    if (old == key) return s;
   }
   return -1;
 }
@@ -153,8 +166,10 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
                                                   float* __restrict__ g_attr, float* __restrict__ g_v) {
   __shared__ int s_key[kSlots];
   __shared__ float s_val[kSlots * kNV];
+  __shared__ int s_list[kSlots];
+  __shared__ int s_nocc;
   for (int i = threadIdx.x; i < kSlots; i += blockDim.x) s_key[i] = -1;
-  for (int i = threadIdx.x; i < kSlots * kNV; i += blockDim.x) s_val[i] = 0.f;
+  if (threadIdx.x == 0) s_nocc = 0;
 
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
   const mer_view vw = views[vi];
@@ -172,7 +187,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   }
   Snap S;
   S.ok = false;
-  if (t >= 0) S = snap_id(v, tri, vw, t);
+  if (t >= 0) S = snap_id<false>(v, tri, vw, t);
   if (t >= 0 && !S.ok) t = -1;
 
   // ---- micro-edge term: fragment gradient (rx, ry, rq) of this pixel
@@ -207,7 +222,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
         }
         continue;
       }
-      const Snap Sn = snap_id(v, tri, vw, tn);
+      const Snap Sn = snap_id<false>(v, tri, vw, tn);
       Snap SA, SB;  // by value: a conditional reference would force the structs to scratch
       if (selfA) {
         SA = S;
@@ -248,7 +263,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   const int head = 63 - __clzll((long long)(F & upto));
   const bool tail = lane == 63 || ((F >> (lane + 1)) & 1ull);
   const bool emit = tail && t >= 0;
-  const int lir = lane & 15, hir = head & 15;  // runs never cross a 16-lane row
+  const RunMask rm = run_mask(lane & 15, head & 15);  // runs never cross a 16-lane row
 
   PixBary pb;
   pb.beta[0] = pb.beta[1] = pb.beta[2] = 0.f;
@@ -263,12 +278,13 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
     gy[k] = pb.beta[k] * ry;
     gz[k] = pb.beta[k] * rq * (-(qk * qk));
   }
-  __syncthreads();  // table cleared
+  __syncthreads();  // keys cleared
   int slot[3] = {-1, -1, -1};
   if (emit) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) slot[k] = slot_of(s_key, S.idx[k]);
+    for (int k = 0; k < 3; ++k) slot[k] = slot_of(s_key, s_val, s_list, &s_nocc, S.idx[k]);
   }
+  __syncthreads();  // every slot this tile uses is claimed and zeroed
 
   // ---- interpolation adjoint and Omega
   if (!(flags & MER_SKIP_INTERP)) {
@@ -283,7 +299,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
       for (int k = 0; k < 3; ++k) {
         if (t >= 0) G[k] += gc * attr[arow[k] + c];
         if (g_attr) {
-          const float s = seg_sum(pb.b[k] * gc, lir, hir);
+          const float s = seg_sum(pb.b[k] * gc, rm);
           if (emit && s != 0.f) {
             if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], s);
             else atomicAdd(g_attr + arow[k] + c, s);
@@ -327,7 +343,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   if (g_v) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float sums[3] = {seg_sum(gx[k], lir, hir), seg_sum(gy[k], lir, hir), seg_sum(gz[k], lir, hir)};
+      const float sums[3] = {seg_sum(gx[k], rm), seg_sum(gy[k], rm), seg_sum(gz[k], rm)};
       if (emit) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -342,10 +358,11 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
 
   // ---- flush: one global atomic per (vertex, component) of this tile
   const int nv = 3 + min(C_a, kCTab);
-  for (int s = threadIdx.x >> 5; s < kSlots; s += (int)(blockDim.x >> 5)) {
+  const int nocc = s_nocc;
+  for (int i = threadIdx.x >> 4; i < nocc; i += (int)(blockDim.x >> 4)) {
+    const int s = s_list[i];
     const int key = s_key[s];
-    if (key < 0) continue;
-    for (int j = threadIdx.x & 31; j < nv; j += 32) {
+    for (int j = threadIdx.x & 15; j < nv; j += 16) {
       const float x = s_val[s * kNV + j];
       if (x == 0.f) continue;
       if (j < 3) {

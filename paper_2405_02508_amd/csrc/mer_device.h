@@ -38,6 +38,9 @@ struct Snap {
   bool ok;
 };
 
+// EXACT_Q: 1/z correctly rounded (the depth key and plane slopes need it);
+// otherwise a hardware reciprocal, for gradient arithmetic only.
+template <bool EXACT_Q = true>
 __device__ __forceinline__ Snap snap_triangle(const float* __restrict__ v, const mer_view& vw,
                                               const int32_t* __restrict__ tri_row) {
   Snap s;
@@ -61,7 +64,7 @@ __device__ __forceinline__ Snap snap_triangle(const float* __restrict__ v, const
     if (fabsf(x) > kGuard || fabsf(y) > kGuard) return s;
     s.X[k] = (int)rintf(x * 256.0f);
     s.Y[k] = (int)rintf(y * 256.0f);
-    s.q[k] = 1.0f / z;
+    s.q[k] = EXACT_Q ? 1.0f / z : __builtin_amdgcn_rcpf(z);
     s.z[k] = z;
   }
   s.D = (long long)(s.X[1] - s.X[0]) * (long long)(s.Y[2] - s.Y[0]) -
@@ -236,8 +239,9 @@ __device__ __forceinline__ PixBary pixel_bary_grad(const Snap& s, int px, int py
 // Slope of the plane through (x_k, y_k, 1/z_k) along axis 0 (x) or 1 (y),
 // binary32 from the snapped vertices, fixed order.
 __device__ __forceinline__ float plane_slope(const Snap& s, int axis) {
-  float dq1 = s.q[1] - s.q[0];
-  float dq2 = s.q[2] - s.q[0];
+  const float q0 = 1.0f / s.z[0], q1 = 1.0f / s.z[1], q2 = 1.0f / s.z[2];  // correctly rounded
+  float dq1 = q1 - q0;
+  float dq2 = q2 - q0;
   float num;
   if (axis == 0) {
     float a = dq1 * (float)((long long)s.Y[2] - s.Y[0]);

@@ -109,15 +109,21 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
       if (pxa <= pxb && pya <= pyb && (pxb - pxa + 1) * (pyb - pya + 1) <= small_px) {
         // small triangle: rasterize its few pixel centres here
         unsigned long long* kv = key + (vw.px_off - px_begin);
-        for (int y = pya; y <= pyb; ++y)
+        const long long dx0 = (long long)R.A[0] * 256, dx1 = (long long)R.A[1] * 256, dx2 = (long long)R.A[2] * 256;
+        for (int y = pya; y <= pyb; ++y) {
+          long long E[3];
+          edge_eval(R, pxa, y, E);  // then step along the row: E += 256 A
           for (int x = pxa; x <= pxb; ++x) {
-            long long E[3];
-            edge_eval(R, x, y, E);
-            if (!covered(E)) continue;
-            float e[3], d;
-            edge_values(R, E, e, d);
-            atomicMax(kv + (long long)y * vw.W + x, vis_key(depth_key(R, e, d), (int)t));
+            if (covered(E)) {
+              float e[3], d;
+              edge_values(R, E, e, d);
+              atomicMax(kv + (long long)y * vw.W + x, vis_key(depth_key(R, e, d), (int)t));
+            }
+            E[0] += dx0;
+            E[1] += dx1;
+            E[2] += dx2;
           }
+        }
       } else if (pxa <= pxb && pya <= pyb) {
         rec[g] = R;
         bb.x0 = (short)pxa;
