@@ -94,6 +94,12 @@ __device__ __forceinline__ Rec make_rec(const Snap& s) {
     r.tl |= tl << k;
     r.q[k] = s.q[k];
   }
+  // bit 3: every |A|, |B| < 2^17, so offsets of up to 46 pixels from a tile
+  // origin, 256 * (A dx + B dy), fit in 31 bits (the tile raster's 32-bit path)
+  bool small = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) small = small && abs(r.A[k]) < (1 << 17) && abs(r.B[k]) < (1 << 17);
+  if (small) r.tl |= 8;
   return r;
 }
 

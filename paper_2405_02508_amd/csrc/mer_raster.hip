@@ -269,6 +269,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    float* __restrict__ depth, float* __restrict__ bary,
                                                    long long* __restrict__ status) {
   constexpr int NT = TW * TH;
+  constexpr bool kEarlyZ = NT == 64;
   __shared__ Rec s_rec[NT];
   __shared__ int s_tid[NT];
   const long long g = blockIdx.x;
@@ -279,6 +280,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const int x0 = (int)(local % tiles_x) * TW, y0 = (int)(local / tiles_x) * TH;
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int px = x0 + lx, py = y0 + ly;
+  const int dxs = lx * 256, dys = ly * 256;
   const bool inside = px < vw.W && py < vw.H;
   const long long tb = tri_base[vi];
 
@@ -310,16 +312,55 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
       const int t = s_tid[j];
       if (t < 0) continue;  // uniform across the block
       const Rec& R = s_rec[j];
+      // per (triangle, tile), uniform: exact edge values at the tile origin
+      long long Et[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        Et[k] = (long long)R.A[k] * (long long)(x0 * 256) + (long long)R.B[k] * (long long)(y0 * 256) + R.C[k];
+      // Early z: the key is a convex combination of the vertices' 1/z up to
+      // a few roundings (< 2^-20 relative), so a lane whose surface is
+      // already nearer than every vertex skips the key.  Enabled for
+      // single-wave tiles only: with multi-wave tiles it produced wrong
+      // index images whose cause was not found (the rule itself checks out
+      // in-kernel), so those tiles compute every covered key.
+      const float qb = kEarlyZ ? fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f) : INFINITY;
+      const float best_q = key_q(best);
+      bool cov;
       long long E[3];
-      edge_eval(R, px, py, E);
-      const bool cov = inside && covered(E);
-      if (__ballot(cov)) {
-        if (cov) {
-          float e[3], d;
-          edge_values(R, E, e, d);
-          const float q = depth_key(R, e, d);
-          const unsigned long long k = vis_key(q, t);
-          best = k > best ? k : best;
+      if (R.tl & 8) {
+        // 32-bit path: E_k > 0  <=>  off_k > -Et_k, with -Et_k clamped to int32
+        int off[3];
+        cov = inside;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          off[k] = __mul24(R.A[k], dxs) + __mul24(R.B[k], dys);  // 24-bit signed products
+          const long long nt = -Et[k];
+          const int thr = nt > 2147483647ll ? 2147483647 : (nt < -2147483647ll ? -2147483647 : (int)nt);
+          cov = cov && off[k] > thr;
+        }
+        const bool need = cov && qb >= best_q;
+        if (__ballot(need)) {
+          if (need) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) E[k] = Et[k] + off[k];
+            float e[3], d;
+            edge_values(R, E, e, d);
+            const unsigned long long k = vis_key(depth_key(R, e, d), t);
+            best = k > best ? k : best;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) E[k] = Et[k] + (long long)R.A[k] * (long long)dxs + (long long)R.B[k] * (long long)dys;
+        cov = inside && covered(E);
+        const bool need = cov && qb >= best_q;
+        if (__ballot(need)) {
+          if (need) {
+            float e[3], d;
+            edge_values(R, E, e, d);
+            const unsigned long long k = vis_key(depth_key(R, e, d), t);
+            best = k > best ? k : best;
+          }
         }
       }
     }
