@@ -92,3 +92,25 @@ def test_plan_rejects_bad_views(L, bad):
 def test_plan_rejects_bad_tile(L):
     with pytest.raises(mer.MerError, match="-4"):
         mer.plan_init(_views([[0, 0, 0, 0, 3, 1, 8, 8]]), (4, 4))
+
+
+def test_calls_reject_null_arguments_before_any_launch(L):
+    """Argument checks run on the host and return an error code; nothing is
+    enqueued, so these run without a GPU."""
+    V = _views([[0, 0, 0, 0, 3, 1, 8, 8]])
+    P = mer.plan_init(V)
+    p = ctypes.byref(P)
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails its checks first
+    assert L.mer_rasterize(p, None, fake, fake, fake, None, None, fake, None) == -1
+    assert L.mer_rasterize(p, fake, fake, fake, fake, None, None, None, None) == -2
+    assert L.mer_interpolate(p, fake, fake, 0, fake, fake, fake, fake, 0, fake, None) == -1
+    assert L.mer_interpolate(p, fake, fake, 64, fake, fake, fake, fake, 1, fake, None) == -1
+    assert L.mer_edge_grad(p, fake, fake, fake, fake, fake, fake, 0, 0, fake, fake, None) == -1
+    assert L.mer_edge_grad(p, fake, fake, fake, fake, fake, fake, 3, 0, fake, None, None) == -2
+    assert L.mer_interpolate_bwd(p, fake, fake, 3, fake, fake, fake, 0, fake, 2, fake, fake, fake, None) == -1
+    assert L.mer_backward_fused(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, 2, 0, fake, fake, fake,
+                                None) == -1
+    assert L.mer_backward_fused(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, 3, 0, fake, fake, None,
+                                None) == -2
+    assert L.mer_status(p, None, None, (ctypes.c_int64 * 4)()) == -2
+    assert L.mer_plan_init(None, 1, None, p) == -1

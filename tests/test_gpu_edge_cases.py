@@ -1,0 +1,124 @@
+"""GPU edge cases against the oracle: empty and degenerate inputs, extreme
+image shapes, culled triangles, invalid index images."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_02508_amd import scenes
+from tests.gpu_util import compare, run_gpu, run_oracle, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(views_spec, seed=0, C_a=3, append_z=False, mask=False):
+    """views_spec: list of (v f32 [n,3], tri i32 [m,3], H, W); attributes random."""
+    rng = np.random.default_rng(seed)
+    per = []
+    attrs = []
+    for i, (v, t, H, W) in enumerate(views_spec):
+        attrs.append(rng.uniform(0, 1, size=(max(v.shape[0], 1), C_a)).astype(np.float32))
+        per.append((np.asarray(v, np.float32).reshape(-1, 3), np.asarray(t, np.int32).reshape(-1, 3), i, i, H, W))
+    return scenes._pack("edge", per, attrs, append_z, mask)
+
+
+def _random_tris(rng, n, H, W, margin=2.0):
+    v = np.concatenate([rng.uniform(-margin, W + margin, (3 * n, 1)), rng.uniform(-margin, H + margin, (3 * n, 1)),
+                        rng.uniform(1.0, 4.0, (3 * n, 1))], 1).astype(np.float32)
+    return v, np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+
+
+def _check(s, seed=0, **kw):
+    g = scenes.image_grad(s, seed)
+    ref = run_oracle(s, g)
+    got = run_gpu(s, g, **kw)
+    compare(got, ref)
+    return got, ref
+
+
+def test_empty_view_and_empty_mesh():
+    say("[edge] empty views")
+    rng = np.random.default_rng(1)
+    v, t = _random_tris(rng, 30, 20, 24)
+    s = _scene([(np.zeros((0, 3)), np.zeros((0, 3)), 9, 13), (v, t, 20, 24), (v[:3], np.zeros((0, 3)), 5, 5)])
+    got, ref = _check(s)
+    vw = s.view(0)
+    assert np.all(got["tri_id"][: vw["H"] * vw["W"]] == -1)
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 37), (37, 1), (2, 16384), (16384, 2), (3, 129)])
+def test_extreme_image_shapes(H, W):
+    say(f"[edge] image {H}x{W}")
+    rng = np.random.default_rng(H * 7 + W)
+    v, t = _random_tris(rng, 60, H, W, margin=4.0)
+    s = _scene([(v, t, H, W)])
+    for tile in [(8, 8), (32, 8)]:
+        got, _ = _check(s, tile=tile)
+
+
+def test_degenerate_and_culled_triangles_match_the_oracle():
+    say("[edge] degenerate / culled")
+    H, W = 40, 48
+    rng = np.random.default_rng(5)
+    v, t = _random_tris(rng, 40, H, W)
+    extra_v = np.array([
+        [10, 10, 2], [20, 20, 2], [30, 30, 2],            # collinear
+        [5, 5, 2], [5, 5, 2], [25, 8, 2],                 # repeated vertex
+        [10, 30, -1], [30, 30, 2], [20, 5, 2],            # behind the camera
+        [10, 30, 5e-4], [30, 30, 2], [20, 5, 2],          # z below the near limit
+        [np.nan, 3, 2], [30, 30, 2], [20, 5, 2],          # non-finite
+        [np.inf, 3, 2], [30, 30, 2], [20, 5, 2],
+        [2e6, 3, 2], [30, 30, 2], [20, 5, 2],             # beyond the guard band
+        [1e5, -1e5, 2], [40, 30, 2], [-1e5, 9e4, 2],      # huge but inside the guard band
+        [3.3, 4.4, 2], [3.3000002, 4.4, 2], [3.3, 4.4000001, 2],   # snaps to zero area
+    ], np.float32)
+    n0 = v.shape[0]
+    vv = np.concatenate([v, extra_v], 0)
+    tt = np.concatenate([t, np.arange(n0, n0 + extra_v.shape[0], dtype=np.int32).reshape(-1, 3),
+                         np.array([[0, 1, n0 + extra_v.shape[0] + 5], [-1, 2, 3]], np.int32)], 0)  # bad indices
+    s = _scene([(vv, tt, H, W)])
+    got, ref = _check(s)
+    _, _, culled = oracle.rasterize(vv, tt, H, W, with_key=True)
+    assert got["status"][0]["culled"] == culled
+    assert culled >= 9
+
+
+def test_vertices_on_pixel_centres_and_shared_edges():
+    """Lattice geometry where the tie rules decide every centre."""
+    say("[edge] lattice ties")
+    rng = np.random.default_rng(9)
+    k = 50
+    P = rng.integers(-2, 50, size=(3 * k, 2)) / 2.0
+    v = np.concatenate([P, rng.choice([1.5, 2.0, 3.0], size=(3 * k, 1))], 1).astype(np.float32)
+    t = np.arange(3 * k, dtype=np.int32).reshape(k, 3)
+    s = _scene([(v, t, 24, 24)])
+    for tile in [(8, 8), (16, 16)]:
+        for sp in [0, -1]:
+            _check(s, tile=tile, small_px=sp)
+
+
+def test_backward_ignores_invalid_index_values():
+    """An index image with out-of-range ids is read as background (no access
+    outside the triangle table)."""
+    import torch
+
+    from paper_2405_02508_amd import mer
+    say("[edge] invalid tri_id values")
+    s = scenes.make_config(1)
+    dev = torch.device("cuda")
+    ctx = mer.Context(s.views, device=dev)
+    v, tri, attr = to_dev(s.v), to_dev(s.tri), to_dev(s.attr)
+    tid = torch.empty(s.n_px, dtype=torch.int32, device=dev)
+    ctx.rasterize(v, tri, tid)
+    bad = tid.clone()
+    bad[::7] = 10 ** 6
+    bad[1::7] = -5
+    img = torch.rand(s.n_px, 3, device=dev)
+    g = torch.rand(s.n_px, 3, device=dev)
+    g_v = torch.zeros_like(v)
+    g_a = torch.zeros_like(attr)
+    ctx.backward(v, tri, bad, attr, img, g, g_a, g_v)
+    out = torch.empty(s.n_px, 3, device=dev)
+    ctx.interpolate(attr, v, tri, bad, out)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g_v).all() and torch.isfinite(g_a).all()
+    assert torch.all(out[::7] == 0)
