@@ -192,67 +192,79 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
 
   // ---- micro-edge term: fragment gradient (rx, ry, rq) of this pixel
   float rx = 0.f, ry = 0.f, rq = 0.f;
-  // a background pixel is never the top side of a pair, so it receives nothing
+  // a background pixel is never the top side of a pair, so it receives nothing.
+  // First the cheap part: which of the four neighbours differ (bit dir of
+  // `pend`); then the wave iterates only as often as its busiest lane has
+  // differing neighbours, each lane taking its next pending pair.
+  unsigned pend = 0;
+  int tn4[4] = {-1, -1, -1, -1};
   if (t >= 0 && !(flags & MER_SKIP_EDGE)) {
-#pragma unroll 1
+#pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
       const int nx = px + (dir == 0 ? -1 : dir == 1 ? 1 : 0);
       const int ny = py + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
       if (nx < 0 || ny < 0 || nx >= vw.W || ny >= vw.H) continue;
-      const long long pn = vw.px_off + (long long)ny * vw.W + nx;
-      int tn = tri_id[pn];
+      int tn = tri_id[vw.px_off + (long long)ny * vw.W + nx];
       if (tn >= vw.n_t || tn < 0) tn = -1;
-      if (tn == t) continue;
-      const bool selfA = dir == 1 || dir == 3;  // self has the smaller coordinate
-      const int axis = dir < 2 ? 0 : 1;
-      const long long pA = selfA ? p : pn, pB = selfA ? pn : p;
-      float acc = 0.f;
-      for (int c = 0; c < C_e; ++c) {
-        const float gs = g[pA * ld_g + c] + g[pB * ld_g + c];
-        const float di = img[pA * C_e + c] - img[pB * C_e + c];
-        acc += gs * di;
-      }
-      const float dLdp = 0.5f * acc;
-      const int tA = selfA ? t : tn, tB = selfA ? tn : t;
-      if (tA < 0 || tB < 0) {
-        // overhang over background: the covered side is on top
-        if ((tA < 0) != selfA) {
-          if (axis == 0) rx += dLdp;
-          else ry += dLdp;
-        }
-        continue;
-      }
-      const Snap Sn = snap_id<false>(v, tri, vw, tn);
-      Snap SA, SB;  // by value: a conditional reference would force the structs to scratch
-      if (selfA) {
-        SA = S;
-        SB = Sn;
-      } else {
-        SA = Sn;
-        SB = S;
-      }
-      const int ax_ = selfA ? px : nx, ay_ = selfA ? py : ny;
-      const int bx_ = selfA ? nx : px, by_ = selfA ? ny : py;
-      const bool cA = contains(SB, ax_, ay_);  // B's triangle holds A's centre
-      const bool cB = contains(SA, bx_, by_);  // A's triangle holds B's centre
-      if (!cA && !cB) continue;                // adjacent: nothing
-      if (cA != cB) {
-        if (cA == selfA) {                     // the contained side is on top
-          if (axis == 0) rx += dLdp;
-          else ry += dLdp;
-        }
-        continue;
-      }
-      if (flags & MER_NO_INTERSECT) continue;
-      const float sA = plane_slope(SA, axis), sB = plane_slope(SB, axis);
-      const float dlt = sB - sA;
-      if (!(dlt > 0.f) || !isfinite(dlt)) continue;
-      const float u = dLdp / dlt;
-      const float ra = selfA ? -sA * u : sB * u;
-      if (axis == 0) rx += ra;
-      else ry += ra;
-      rq += selfA ? u : -u;
+      tn4[dir] = tn;
+      if (tn != t) pend |= 1u << dir;
     }
+  }
+#pragma unroll 1
+  while (__ballot(pend != 0)) {
+    if (pend == 0) continue;
+    const int dir = __builtin_ctz(pend);
+    pend &= pend - 1;
+    const int tn = dir == 0 ? tn4[0] : dir == 1 ? tn4[1] : dir == 2 ? tn4[2] : tn4[3];
+    const int nx = px + (dir == 0 ? -1 : dir == 1 ? 1 : 0);
+    const int ny = py + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
+    const long long pn = vw.px_off + (long long)ny * vw.W + nx;
+    const bool selfA = dir == 1 || dir == 3;  // self has the smaller coordinate
+    const int axis = dir < 2 ? 0 : 1;
+    const long long pA = selfA ? p : pn, pB = selfA ? pn : p;
+    float acc = 0.f;
+    for (int c = 0; c < C_e; ++c) {
+      const float gs = g[pA * ld_g + c] + g[pB * ld_g + c];
+      const float di = img[pA * C_e + c] - img[pB * C_e + c];
+      acc += gs * di;
+    }
+    const float dLdp = 0.5f * acc;
+    if (tn < 0) {
+      // overhang over background: this (covered) side is on top
+      if (axis == 0) rx += dLdp;
+      else ry += dLdp;
+      continue;
+    }
+    const Snap Sn = snap_id<false>(v, tri, vw, tn);
+    Snap SA, SB;  // by value: a conditional reference would force the structs to scratch
+    if (selfA) {
+      SA = S;
+      SB = Sn;
+    } else {
+      SA = Sn;
+      SB = S;
+    }
+    const int ax_ = selfA ? px : nx, ay_ = selfA ? py : ny;
+    const int bx_ = selfA ? nx : px, by_ = selfA ? ny : py;
+    const bool cA = contains(SB, ax_, ay_);  // B's triangle holds A's centre
+    const bool cB = contains(SA, bx_, by_);  // A's triangle holds B's centre
+    if (!cA && !cB) continue;                // adjacent: nothing
+    if (cA != cB) {
+      if (cA == selfA) {                     // the contained side is on top
+        if (axis == 0) rx += dLdp;
+        else ry += dLdp;
+      }
+      continue;
+    }
+    if (flags & MER_NO_INTERSECT) continue;
+    const float sA = plane_slope(SA, axis), sB = plane_slope(SB, axis);
+    const float dlt = sB - sA;
+    if (!(dlt > 0.f) || !isfinite(dlt)) continue;
+    const float u = dLdp / dlt;
+    const float ra = selfA ? -sA * u : sB * u;
+    if (axis == 0) rx += ra;
+    else ry += ra;
+    rq += selfA ? u : -u;
   }
 
   // ---- runs of equal triangle along each 16-pixel row of the wave
