@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
             b1 = bb.y;
             b2 = (1.0f - b0) - b1;
           } else {
-            const Snap sn = snap_triangle(v, vw, row);
+            const Snap sn = snap_triangle<false>(v, vw, row);
             ok = sn.ok;
             if (ok) {
               const PixBary pb = pixel_bary(sn, (int)(local % vw.W), (int)(local / vw.W));
@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ v
   pb.beta[0] = pb.beta[1] = pb.beta[2] = 0.f;
   pb.b[0] = pb.b[1] = pb.b[2] = 0.f;
   pb.Wq = 1.f;
-  if (t >= 0) pb = pixel_bary_grad(S, px, py);
+  if (t >= 0) pb = pixel_bary(S, px, py);
   float gx[3], gy[3], gz[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {

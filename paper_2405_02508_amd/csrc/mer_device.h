@@ -190,47 +190,39 @@ __device__ __forceinline__ bool contains(const Snap& s, int px, int py) {
   return covered_at(s, E);
 }
 
-// Screen barycentrics (exact edge values / D), perspective-correct b, W = sum e_k q_k / d.
+// Screen barycentrics beta_k = e_k / |D| from the exact edge values,
+// perspective-correct b_k = beta_k q_k / W with W = sum_k beta_k q_k (the
+// interpolated 1/z), using hardware reciprocals (about 1 ulp each).  Inside a
+// triangle with |D| < 2^31 every e_k lies in [0, |D|] and converts to binary32
+// in one instruction; otherwise the 64-bit conversion is used.
 struct PixBary {
   float beta[3];
   float b[3];
-  float Wq;  // interpolated 1/z
+  float Wq;
 };
+
+__device__ __forceinline__ bool fits_i32(long long x) { return x == (long long)(int)x; }
 
 __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
   long long E[3];
   edge_at(s, px, py, E);
-  float e[3];
-  e[0] = (float)E[0];
-  e[1] = (float)E[1];
-  e[2] = (float)E[2];
-  const float d = (float)(E[0] + E[1] + E[2]);
-  PixBary o;
-  float w[3];
+  const long long Dabs = s.D < 0 ? -s.D : s.D;  // = E[0] + E[1] + E[2]
+  float e[3], d;
+  if (fits_i32(E[0]) && fits_i32(E[1]) && fits_i32(E[2]) && Dabs < 2147483648ll) {
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    o.beta[k] = e[k] / d;
-    w[k] = o.beta[k] * s.q[k];
+    for (int k = 0; k < 3; ++k) e[k] = (float)(int)E[k];
+    d = (float)(int)Dabs;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = (float)E[k];
+    d = (float)Dabs;
   }
-  float W = (w[0] + w[1]) + w[2];
-  o.b[0] = w[0] / W;
-  o.b[1] = w[1] / W;
-  o.b[2] = (1.0f - o.b[0]) - o.b[1];
-  o.Wq = W;
-  return o;
-}
-
-// Barycentrics for gradients only: same quantities as pixel_bary, with
-// reciprocals in place of correctly rounded divisions.
-__device__ __forceinline__ PixBary pixel_bary_grad(const Snap& s, int px, int py) {
-  long long E[3];
-  edge_at(s, px, py, E);
-  const float id = __builtin_amdgcn_rcpf((float)(E[0] + E[1] + E[2]));
+  const float id = __builtin_amdgcn_rcpf(d);
   PixBary o;
   float w[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    o.beta[k] = (float)E[k] * id;
+    o.beta[k] = e[k] * id;
     w[k] = o.beta[k] * s.q[k];
   }
   const float W = (w[0] + w[1]) + w[2];

@@ -257,6 +257,26 @@ __global__ void __launch_bounds__(256) k_fill(const mer_view* __restrict__ views
 }
 
 // --------------------------------------------------------------- raster
+// Per (record, tile) constants, prepared by one lane per record and read by
+// every lane of the tile from LDS (same address in every lane: broadcast).
+// A record is "fast" when |A|, |B| < 2^17 (pixel offsets from the tile origin
+// fit in 31 bits) and |D| < 2^31: a covered centre's unbiased edge values lie
+// in [0, |D|], so they are the 32-bit sum of the tile-origin values' low
+// halves and the offsets, and d = |D| is the same at every pixel.
+struct __align__(16) TileRec {
+  int A[3];
+  int B[3];
+  int u0[3];   // low 32 bits of the unbiased edge values at the tile origin
+  int thr[3];  // covered iff offset_k > thr_k (minus the biased value, clamped)
+  float q[3];  // vertex 1/z
+  float d;     // (float)|D|
+  float qb;    // early-z bound: no key of this record exceeds it
+  unsigned tneg;  // 0xFFFFFFFF - t, low half of the visibility key
+  int t;       // triangle index in the view, -1: skip
+  int fast;
+};
+static_assert(sizeof(TileRec) == 80, "tile record layout");
+
 template <int TW, int TH>
 __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ views, int n_views,
                                                    const long long* __restrict__ tri_base,
@@ -270,8 +290,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    long long* __restrict__ status) {
   constexpr int NT = TW * TH;
   constexpr bool kEarlyZ = NT == 64;
-  __shared__ Rec s_rec[NT];
-  __shared__ int s_tid[NT];
+  __shared__ TileRec s_tr[NT];
   const long long g = blockIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
   const mer_view vw = views[vi];
@@ -304,63 +323,78 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         const BBox bb = bbox[r];
         keep = bb.x0 <= bb.x1 && bb.x1 >= x0 && bb.x0 < x0 + TW && bb.y1 >= y0 && bb.y0 < y0 + TH;
       }
-      s_tid[threadIdx.x] = keep ? (int)(r - tb) : -1;
-      if (keep) s_rec[threadIdx.x] = rec[r];
+      TileRec o;
+      o.t = -1;
+      if (keep) {
+        const Rec R = rec[r];
+        long long Dabs = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          // exact biased edge value at the tile origin's centre
+          const long long Et = (long long)R.A[k] * (long long)(x0 * 256) + (long long)R.B[k] * (long long)(y0 * 256) + R.C[k];
+          const long long u = Et - ((R.tl >> k) & 1);
+          Dabs += u;  // the unbiased values sum to |D| at every point
+          const long long nt = -Et;
+          o.thr[k] = nt > 2147483647ll ? 2147483647 : (nt < -2147483647ll ? -2147483647 : (int)nt);
+          o.u0[k] = (int)(unsigned)(unsigned long long)u;
+          o.A[k] = R.A[k];
+          o.B[k] = R.B[k];
+          o.q[k] = R.q[k];
+        }
+        o.d = (float)Dabs;
+        o.fast = (R.tl & 8) && Dabs < 2147483648ll;
+        // Early z: the key is a convex combination of the vertices' 1/z up to
+        // a few roundings (< 2^-20 relative), so a lane whose surface is
+        // already nearer than every vertex skips the key.  Enabled for
+        // single-wave tiles only: with multi-wave tiles it produced wrong
+        // index images whose cause was not found (the rule itself checks out
+        // in-kernel), so those tiles compute every covered key.
+        o.qb = kEarlyZ ? fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f) : INFINITY;
+        o.t = (int)(r - tb);
+        o.tneg = 0xFFFFFFFFu - (unsigned)o.t;
+      }
+      s_tr[threadIdx.x] = o;
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
-      const int t = s_tid[j];
+      const TileRec T = s_tr[j];  // five 16-byte LDS broadcasts
+      const int t = T.t;
       if (t < 0) continue;  // uniform across the block
-      const Rec& R = s_rec[j];
-      // per (triangle, tile), uniform: exact edge values at the tile origin
-      long long Et[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        Et[k] = (long long)R.A[k] * (long long)(x0 * 256) + (long long)R.B[k] * (long long)(y0 * 256) + R.C[k];
-      // Early z: the key is a convex combination of the vertices' 1/z up to
-      // a few roundings (< 2^-20 relative), so a lane whose surface is
-      // already nearer than every vertex skips the key.  Enabled for
-      // single-wave tiles only: with multi-wave tiles it produced wrong
-      // index images whose cause was not found (the rule itself checks out
-      // in-kernel), so those tiles compute every covered key.
-      const float qb = kEarlyZ ? fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f) : INFINITY;
       const float best_q = key_q(best);
-      bool cov;
-      long long E[3];
-      if (R.tl & 8) {
-        // 32-bit path: E_k > 0  <=>  off_k > -Et_k, with -Et_k clamped to int32
+      if (T.fast) {
+        // 32-bit path: covered iff off_k > thr_k for all k; then the unbiased
+        // edge values are u0_k + off_k exactly (mod 2^32 and in [0, 2^31))
         int off[3];
-        cov = inside;
+        bool cov = inside & (T.qb >= best_q);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          off[k] = __mul24(R.A[k], dxs) + __mul24(R.B[k], dys);  // 24-bit signed products
-          const long long nt = -Et[k];
-          const int thr = nt > 2147483647ll ? 2147483647 : (nt < -2147483647ll ? -2147483647 : (int)nt);
-          cov = cov && off[k] > thr;
+          off[k] = __mul24(T.A[k], dxs) + __mul24(T.B[k], dys);  // 24-bit signed products
+          cov &= off[k] > T.thr[k];
         }
-        const bool need = cov && qb >= best_q;
-        if (__ballot(need)) {
-          if (need) {
+        if (cov) {
+          float e[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) E[k] = Et[k] + off[k];
-            float e[3], d;
-            edge_values(R, E, e, d);
-            const unsigned long long k = vis_key(depth_key(R, e, d), t);
-            best = k > best ? k : best;
-          }
+          for (int k = 0; k < 3; ++k) e[k] = (float)(int)((unsigned)T.u0[k] + (unsigned)off[k]);
+          float a = e[0] * T.q[0];
+          float b = e[1] * T.q[1];
+          float c = e[2] * T.q[2];
+          float nq = a + b;
+          nq = nq + c;
+          const float qk = nq / T.d;
+          const unsigned long long k = ((unsigned long long)__float_as_uint(qk) << 32) | T.tneg;
+          best = k > best ? k : best;
         }
       } else {
+        const Rec R = rec[tb + __builtin_amdgcn_readfirstlane(t)];
+        long long E[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) E[k] = Et[k] + (long long)R.A[k] * (long long)dxs + (long long)R.B[k] * (long long)dys;
-        cov = inside && covered(E);
-        const bool need = cov && qb >= best_q;
-        if (__ballot(need)) {
-          if (need) {
-            float e[3], d;
-            edge_values(R, E, e, d);
-            const unsigned long long k = vis_key(depth_key(R, e, d), t);
-            best = k > best ? k : best;
-          }
+        for (int k = 0; k < 3; ++k)
+          E[k] = (long long)R.A[k] * (long long)(px * 256) + (long long)R.B[k] * (long long)(py * 256) + R.C[k];
+        if (inside && covered(E) && T.qb >= best_q) {
+          float e[3], d;
+          edge_values(R, E, e, d);
+          const unsigned long long k = vis_key(depth_key(R, e, d), t);
+          best = k > best ? k : best;
         }
       }
     }
@@ -373,7 +407,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   if (bary) {
     float b0 = 0.f, b1 = 0.f;
     if (t >= 0) {
-      const PixBary pb = pixel_bary(snap_triangle(v, vw, tri + (vw.t_off + t) * 3), px, py);
+      const PixBary pb = pixel_bary(snap_triangle<false>(v, vw, tri + (vw.t_off + t) * 3), px, py);
       b0 = pb.b[0];
       b1 = pb.b[1];
     }
