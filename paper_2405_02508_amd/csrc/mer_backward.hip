@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
     if (valid) {
       int t = tri_id[p];
       if (t >= 0 && t < vw.n_t) {
-        const int32_t* row = tri + (vw.t_off + t) * 3;
+        const int32_t* row = tri_row(tri, vw, (int)t);
         idx[0] = row[0];
         idx[1] = row[1];
         idx[2] = row[2];
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
 // ------------------------------------------------------------- backward
 template <bool EXACT_Q>
 __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, const mer_view& vw, int t) {
-  return snap_triangle<EXACT_Q>(v, vw, tri + (vw.t_off + t) * 3);
+  return snap_triangle<EXACT_Q>(v, vw, tri_row(tri, vw, (int)t));
 }
 
 // Segmented inclusive sum over lanes [hir, lir] of one 16-lane row of a

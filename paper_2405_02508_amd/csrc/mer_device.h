@@ -40,37 +40,55 @@ struct Snap {
 
 // EXACT_Q: 1/z correctly rounded (the depth key and plane slopes need it);
 // otherwise a hardware reciprocal, for gradient arithmetic only.
+// Branch-free over the three vertices: the nine coordinates are loaded
+// together (only when all three indices are in range) and every check is
+// folded into ok, so a culled triangle costs the same as a kept one.
 template <bool EXACT_Q = true>
 __device__ __forceinline__ Snap snap_triangle(const float* __restrict__ v, const mer_view& vw,
-                                              const int32_t* __restrict__ tri_row) {
+                                              const int32_t* __restrict__ row) {
   Snap s;
-  s.ok = false;
-  s.D = 0;
+  bool ok = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    int i = tri_row[k];
-    s.idx[k] = i;
-    s.X[k] = s.Y[k] = 0;
-    s.q[k] = s.z[k] = 0.f;
+    s.idx[k] = row[k];
+    ok &= (unsigned)s.idx[k] < (unsigned)vw.n_v;
+  }
+  float p[9];
+#pragma unroll
+  for (int j = 0; j < 9; ++j) p[j] = 0.f;
+  if (ok) {
+    const float* vb = v + vw.v_off * 3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const float* q = vb + (size_t)(unsigned)s.idx[k] * 3u;
+      p[3 * k] = q[0];
+      p[3 * k + 1] = q[1];
+      p[3 * k + 2] = q[2];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    int i = s.idx[k];
-    if (i < 0 || i >= vw.n_v) return s;
-    const float* p = v + (vw.v_off + (long long)i) * 3;
-    float x = p[0], y = p[1], z = p[2];
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return s;
-    if (!(z > kZNear)) return s;
-    if (fabsf(x) > kGuard || fabsf(y) > kGuard) return s;
+    const float x = p[3 * k], y = p[3 * k + 1], z = p[3 * k + 2];
+    // z > near is false for NaN; |x|, |y| <= guard is false for NaN and inf
+    ok &= (z > kZNear) & (z < INFINITY) & (fabsf(x) <= kGuard) & (fabsf(y) <= kGuard);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float x = ok ? p[3 * k] : 0.f, y = ok ? p[3 * k + 1] : 0.f, z = ok ? p[3 * k + 2] : 1.f;
     s.X[k] = (int)rintf(x * 256.0f);
     s.Y[k] = (int)rintf(y * 256.0f);
-    s.q[k] = EXACT_Q ? 1.0f / z : __builtin_amdgcn_rcpf(z);
-    s.z[k] = z;
+    s.q[k] = ok ? (EXACT_Q ? 1.0f / z : __builtin_amdgcn_rcpf(z)) : 0.f;
+    s.z[k] = ok ? z : 0.f;
   }
   s.D = (long long)(s.X[1] - s.X[0]) * (long long)(s.Y[2] - s.Y[0]) -
         (long long)(s.X[2] - s.X[0]) * (long long)(s.Y[1] - s.Y[0]);
-  s.ok = s.D != 0;
+  s.ok = ok && s.D != 0;
   return s;
+}
+
+// Row of view-local triangle t (0 <= t < n_t): per-view base plus a 32x32-bit offset.
+__device__ __forceinline__ const int32_t* tri_row(const int32_t* tri, const mer_view& vw, int t) {
+  return tri + vw.t_off * 3 + (size_t)(unsigned)t * 3u;
 }
 
 // Build the coverage record from a snapped triangle.

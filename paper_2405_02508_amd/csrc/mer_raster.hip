@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
     const int vi = wave_bucket(tri_base, n_views, g);
     const mer_view vw = views[vi];
     const long long t = g - tri_base[vi];
-    const Snap s = snap_triangle(v, vw, tri + (vw.t_off + t) * 3);
+    const Snap s = snap_triangle(v, vw, tri_row(tri, vw, (int)t));
     BBox bb = {1, 1, 0, 0};
     if (!s.ok) {
       culled = true;
@@ -407,7 +407,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   if (bary) {
     float b0 = 0.f, b1 = 0.f;
     if (t >= 0) {
-      const PixBary pb = pixel_bary(snap_triangle<false>(v, vw, tri + (vw.t_off + t) * 3), px, py);
+      const PixBary pb = pixel_bary(snap_triangle<false>(v, vw, tri_row(tri, vw, (int)t)), px, py);
       b0 = pb.b[0];
       b1 = pb.b[1];
     }
