@@ -134,14 +134,14 @@ __device__ __forceinline__ float seg_sum(float x, const RunMask& m) {
 //  4. the workgroup flushes the table with one global float atomic per
 //     (vertex, component).  Vertices that do not fit the table, and
 //     attribute channels beyond kCTab, go straight to global atomics.
-constexpr int kSlots = 512;  // vertex slots per workgroup
+constexpr int kSlots = 256;  // vertex slots per workgroup
 constexpr int kCTab = 8;     // attribute channels reduced in LDS
 constexpr int kNV = 3 + kCTab;
 
 // Find or claim the slot of vertex `key`; a new slot has its values zeroed
 // and is appended to the occupied list.  -1 when the probe limit is hit.
 __device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, int* s_nocc, int key) {
-  unsigned h = ((unsigned)key * 2654435761u) >> 23;  // 9 bits
+  unsigned h = ((unsigned)key * 2654435761u) >> 24;  // 8 bits
 #pragma unroll 1
   for (int probe = 0; probe < 32; ++probe) {
     const int s = (int)((h + probe) & (kSlots - 1));
@@ -157,7 +157,7 @@ __device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, in
   return -1;
 }
 
-__global__ void __launch_bounds__(256) k_backward(const mer_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_backward(const mer_view* __restrict__ views, int n_views,
                                                   const long long* __restrict__ btile_base,
                                                   const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                   const int32_t* __restrict__ tri_id, const float* __restrict__ attr,
