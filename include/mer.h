@@ -89,7 +89,9 @@ typedef struct mer_plan {
 } mer_plan;
 
 /* Validate the host copy of the view table (H, W in [1, 32767], n_v, n_t >= 0,
- * offsets >= 0) and fill *plan.  tun may be NULL (8x8 tiles, default pool).
+ * offsets >= 0, views packed in order; sum n_t <= INT_MAX and fewer than
+ * INT_MAX raster tiles over all views) and fill *plan.  tun may be NULL (8x8
+ * tiles, default pool).
  * Reads host memory only.  MER_EINVAL on a bad view, MER_ETUNING on an
  * unsupported tile shape. */
 int mer_plan_init(const mer_view *views_host, int n_views, const mer_tuning *tun, mer_plan *plan);

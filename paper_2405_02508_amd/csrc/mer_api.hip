@@ -48,7 +48,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
     tiles += (int64_t)((w.W + tw - 1) / tw) * ((w.H + th - 1) / th);
     btiles += (int64_t)((w.W + 15) / 16) * ((w.H + 15) / 16);
   }
-  if (tris > INT_MAX) return MER_EINVAL;
+  if (tris > INT_MAX || tiles >= INT_MAX || btiles >= INT_MAX) return MER_EINVAL;
   P->n_views = n_views;
   P->px_begin = views[0].px_off;
   P->tile_w = tw;

@@ -77,7 +77,62 @@ struct BBox {
   short x0, y0, x1, y1;  // inclusive pixel range; x0 > x1 when empty/culled
 };
 
-__global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ views, int n_views,
+// Every tile (global index) whose box of pixel centres inside bb the record
+// may cover (box_may_cover); the count and fill passes use the same test.
+template <typename F>
+__device__ __forceinline__ void for_each_tile(const Rec& R, const BBox& bb, const mer_view& vw, long long base,
+                                              int tw_log2, int th_log2, F f) {
+  const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
+  for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
+    for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx) {
+      const int bx0 = max(tx << tw_log2, (int)bb.x0), bx1 = min(((tx + 1) << tw_log2) - 1, (int)bb.x1);
+      const int by0 = max(ty << th_log2, (int)bb.y0), by1 = min(((ty + 1) << th_log2) - 1, (int)bb.y1);
+      if (box_may_cover(R, bx0, by0, bx1, by1)) f((int)(base + (long long)ty * tiles_x + tx));
+    }
+}
+
+// Workgroup table of tile counters: the count and fill passes add into LDS
+// and touch each tile's global counter once per workgroup.  The table stops
+// taking new tiles at 3/4 occupancy (a workgroup of large triangles can meet
+// thousands of tiles); tiles left out use their global counter directly.
+constexpr int kBinBlock = 256;  // threads per workgroup of the count and fill passes
+constexpr int kBinLog2 = 10;    // table of 2^kBinLog2 tile slots
+constexpr int kBinSlots = 1 << kBinLog2;
+constexpr int kBinFull = kBinSlots * 3 / 4;
+constexpr int kBinProbe = 16;
+
+__device__ __forceinline__ void clear_tile_table(int* s_tkey, int* s_tcnt, int* s_nocc) {
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x) {
+    s_tkey[i] = -1;
+    s_tcnt[i] = 0;
+  }
+  if (threadIdx.x == 0) *s_nocc = 0;
+}
+
+// Slot of tile `key`, inserting it if INSERT and the table has room; -1 if
+// absent.  After the inserting phase (and a barrier) lookups are stable.
+template <bool INSERT>
+__device__ __forceinline__ int tile_slot(int* s_tkey, int* s_nocc, int key) {
+  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kBinLog2);
+#pragma unroll 1
+  for (int probe = 0; probe < kBinProbe; ++probe) {
+    const int sl = (int)((h + probe) & (kBinSlots - 1));
+    const int cur = s_tkey[sl];
+    if (cur == key) return sl;
+    if (cur == -1) {
+      if (!INSERT || *s_nocc >= kBinFull) return -1;
+      const int old = atomicCAS(&s_tkey[sl], -1, key);
+      if (old == -1) {
+        atomicAdd(s_nocc, 1);
+        return sl;
+      }
+      if (old == key) return sl;
+    }
+  }
+  return -1;
+}
+
+__global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict__ views, int n_views,
                                                const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                const long long* __restrict__ tri_base,
                                                const long long* __restrict__ tile_base, long long total_tris,
@@ -85,6 +140,9 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
                                                Rec* __restrict__ rec, BBox* __restrict__ bbox,
                                                int* __restrict__ count, unsigned long long* __restrict__ key,
                                                long long* __restrict__ status) {
+  __shared__ int s_tkey[kBinSlots], s_tcnt[kBinSlots], s_nocc;
+  clear_tile_table(s_tkey, s_tcnt, &s_nocc);
+  __syncthreads();
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool culled = false;
   if (g < total_tris) {
@@ -130,18 +188,19 @@ __global__ void __launch_bounds__(256) k_setup(const mer_view* __restrict__ view
         bb.x1 = (short)pxb;
         bb.y0 = (short)pya;
         bb.y1 = (short)pyb;
-        const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
-        const long long base = tile_base[vi];
-        for (int ty = pya >> th_log2; ty <= (pyb >> th_log2); ++ty)
-          for (int tx = pxa >> tw_log2; tx <= (pxb >> tw_log2); ++tx) {
-            const int bx0 = max(tx << tw_log2, pxa), bx1 = min(((tx + 1) << tw_log2) - 1, pxb);
-            const int by0 = max(ty << th_log2, pya), by1 = min(((ty + 1) << th_log2) - 1, pyb);
-            if (box_may_cover(R, bx0, by0, bx1, by1)) atomicAdd(count + base + (long long)ty * tiles_x + tx, 1);
-          }
+        for_each_tile(R, bb, vw, tile_base[vi], tw_log2, th_log2, [&](int gt) {
+          const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
+          if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
+          else atomicAdd(count + gt, 1);
+        });
       }
     }
     bbox[g] = bb;
   }
+  __syncthreads();
+  // one global atomic per (workgroup, tile)
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x)
+    if (s_tkey[i] >= 0) atomicAdd(count + s_tkey[i], s_tcnt[i]);
   // one atomic per wave for the culled count
   unsigned long long m = __ballot(culled);
   if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd((unsigned long long*)status + 1, (unsigned long long)__popcll(m));
@@ -228,32 +287,56 @@ __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ coun
 }
 
 // ----------------------------------------------------------------- fill
-__global__ void __launch_bounds__(256) k_fill(const mer_view* __restrict__ views, int n_views,
+// Each workgroup counts its entries per tile in LDS, reserves one contiguous
+// range per tabled tile with a single global atomic, then writes its entries:
+// into that range, or for a tile the table did not take, at a position taken
+// from the tile's global counter.
+__global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__ views, int n_views,
                                               const long long* __restrict__ tri_base,
                                               const long long* __restrict__ tile_base, long long total_tris,
                                               int tw_log2, int th_log2, const Rec* __restrict__ rec,
                                               const BBox* __restrict__ bbox,
                                               int* __restrict__ count, const int* __restrict__ offs,
                                               long long bin_cap, int* __restrict__ bins) {
+  __shared__ int s_tkey[kBinSlots], s_tcnt[kBinSlots], s_nocc;
+  clear_tile_table(s_tkey, s_tcnt, &s_nocc);
+  __syncthreads();
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= total_tris) return;
-  const BBox bb = bbox[g];
-  if (bb.x0 > bb.x1) return;
-  const int vi = wave_bucket(tri_base, n_views, g);
-  const mer_view vw = views[vi];
-  const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
-  const long long base = tile_base[vi];
-  const Rec R = rec[g];
-  for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
-    for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx) {
-      const int bx0 = max(tx << tw_log2, (int)bb.x0), bx1 = min(((tx + 1) << tw_log2) - 1, (int)bb.x1);
-      const int by0 = max(ty << th_log2, (int)bb.y0), by1 = min(((ty + 1) << th_log2) - 1, (int)bb.y1);
-      if (!box_may_cover(R, bx0, by0, bx1, by1)) continue;  // same test as the count pass
-      const long long tile = base + (long long)ty * tiles_x + tx;
-      const int slot = atomicSub(count + tile, 1) - 1;
-      const long long pos = (long long)offs[tile] + slot;
-      if (pos < bin_cap) bins[pos] = (int)g;
+  BBox bb = {1, 1, 0, 0};
+  if (g < total_tris) bb = bbox[g];
+  const bool live = bb.x0 <= bb.x1;
+  Rec R;
+  mer_view vw;
+  long long base = 0;
+  if (live) {
+    const int vi = wave_bucket(tri_base, n_views, g);
+    vw = views[vi];
+    base = tile_base[vi];
+    R = rec[g];
+    for_each_tile(R, bb, vw, base, tw_log2, th_log2, [&](int gt) {
+      const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
+      if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
+    });
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x) {
+    const int gt = s_tkey[i];
+    if (gt >= 0) {
+      const int n = s_tcnt[i];
+      s_tcnt[i] = offs[gt] + atomicSub(count + gt, n) - n;  // first position of this workgroup's range
     }
+  }
+  __syncthreads();
+  if (live) {
+    // the table is frozen: a tile in it takes the next position of the
+    // workgroup's range, any other tile its own global counter
+    for_each_tile(R, bb, vw, base, tw_log2, th_log2, [&](int gt) {
+      const int sl = tile_slot<false>(s_tkey, &s_nocc, gt);
+      const long long pos = sl >= 0 ? (long long)atomicAdd(&s_tcnt[sl], 1)
+                                    : (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
+      if (pos < bin_cap) bins[pos] = (int)g;
+    });
+  }
 }
 
 // --------------------------------------------------------------- raster
@@ -439,7 +522,7 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)min((nt + 255) / 256, 4096ll)), dim3(256), 0, st, count, nt);
   hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)min((npx + 255) / 256, 8192ll)), dim3(256), 0, st, key, npx);
   if (P->total_tris > 0) {
-    hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+    hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
                        v, tri, tri_base, tile_base, P->total_tris, twl, thl, P->small_px, P->px_begin, rec, bbox, count,
                        key, status);
   }
@@ -447,7 +530,7 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(256), 0, st, part, P->n_part);
   hipLaunchKernelGGL(k_scan_final, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part, offs, status);
   if (P->total_tris > 0) {
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
                        tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, offs, P->bin_cap, bins);
   }
 #define MER_RASTER(TW, TH)                                                                                       \

@@ -89,6 +89,16 @@ def test_plan_rejects_bad_views(L, bad):
         mer.plan_init(_views(bad))
 
 
+def test_plan_rejects_too_many_tiles(L):
+    # 128 views of 32767^2 pixels: 128 * 4096^2 = 2^31 tiles of 8x8 (the tile
+    # counters and bin offsets are 32-bit); 127 such views are accepted
+    n = 32767 * 32767
+    rows = [[0, 0, 0, i * n, 3, 1, 32767, 32767] for i in range(128)]
+    with pytest.raises(mer.MerError, match="-1"):
+        mer.plan_init(_views(rows))
+    assert mer.plan_init(_views(rows[:127]), (16, 16)).total_tiles == 127 * 2048 * 2048
+
+
 def test_plan_rejects_bad_tile(L):
     with pytest.raises(mer.MerError, match="-4"):
         mer.plan_init(_views([[0, 0, 0, 0, 3, 1, 8, 8]]), (4, 4))
