@@ -50,13 +50,16 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
             b1 = bb.y;
             b2 = (1.0f - b0) - b1;
           } else {
-            const Snap sn = snap_triangle<false>(v, vw, row);
+            // exactly as the rasterizer's resolve computes them
+            const Snap sn = snap_triangle(v, vw, row);
             ok = sn.ok;
             if (ok) {
-              const PixBary pb = pixel_bary(sn, (int)(local % vw.W), (int)(local / vw.W));
-              b0 = pb.b[0];
-              b1 = pb.b[1];
-              b2 = pb.b[2];
+              float a, b, n;
+              resolve_products(sn, (int)(local % vw.W), (int)(local / vw.W), a, b, n);
+              const float r = __builtin_amdgcn_rcpf(n);
+              b0 = a * r;
+              b1 = b * r;
+              b2 = (1.0f - b0) - b1;
             }
           }
         }

@@ -252,6 +252,21 @@ __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
   return o;
 }
 
+// Depth-key products at pixel (px, py) of snapped triangle s (EXACT_Q):
+// a = e0 q0, b = e1 q1 and n = (a + b) + e2 q2 from the exact edge values and
+// correctly rounded 1/z.  n / |D| is the depth key, and (a, b) / n are the
+// perspective-correct barycentrics b0, b1 (beta_k q_k / W with |D| cancelled);
+// the rasterizer keeps these products for the winning candidate.
+__device__ __forceinline__ void resolve_products(const Snap& s, int px, int py, float& a, float& b, float& n) {
+  long long E[3];
+  edge_at(s, px, py, E);
+  a = (float)E[0] * s.q[0];
+  b = (float)E[1] * s.q[1];
+  const float c = (float)E[2] * s.q[2];
+  n = a + b;
+  n = n + c;
+}
+
 // Slope of the plane through (x_k, y_k, 1/z_k) along axis 0 (x) or 1 (y),
 // binary32 from the snapped vertices, fixed order.
 __device__ __forceinline__ float plane_slope(const Snap& s, int axis) {

@@ -360,7 +360,7 @@ struct __align__(16) TileRec {
 };
 static_assert(sizeof(TileRec) == 80, "tile record layout");
 
-template <int TW, int TH>
+template <int TW, int TH, bool BARY>
 __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ views, int n_views,
                                                    const long long* __restrict__ tri_base,
                                                    const long long* __restrict__ tile_base,
@@ -375,12 +375,13 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   constexpr bool kEarlyZ = NT == 64;
   __shared__ TileRec s_tr[NT];
   const long long g = blockIdx.x;
+  const int lt = threadIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
   const mer_view vw = views[vi];
   const long long local = g - tile_base[vi];
   const int tiles_x = (vw.W + TW - 1) / TW;
   const int x0 = (int)(local % tiles_x) * TW, y0 = (int)(local / tiles_x) * TH;
-  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int lx = lt % TW, ly = lt / TW;
   const int px = x0 + lx, py = y0 + ly;
   const int dxs = lx * 256, dys = ly * 256;
   const bool inside = px < vw.W && py < vw.H;
@@ -390,19 +391,24 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const bool overflow = end > bin_cap;
   // overflow fallback: scan every record of the view, filtered by bbox
   const long long n_items = overflow ? (tri_base[vi + 1] - tb) : (end - start);
-  if (overflow && threadIdx.x == 0) atomicAdd((unsigned long long*)status, 1ull);
+  if (overflow && lt == 0) atomicAdd((unsigned long long*)status, 1ull);
 
   const long long p = vw.px_off + (long long)py * vw.W + px;
-  unsigned long long best = inside ? key[p - px_begin] : 0ull;
+  // key: the small-triangle pass's result, or NULL when that pass is off
+  unsigned long long best = inside && key ? key[p - px_begin] : 0ull;
+  // products e_k q_k (k = 0, 1) and their sum over k of the current winner
+  // when it came from this loop: the barycentrics without another gather
+  float wa = 0.f, wb = 0.f, wn = 0.f;
+  bool own = false;
   for (long long c0 = 0; c0 < n_items; c0 += NT) {
     const int n = (int)min((long long)NT, n_items - c0);
-    if (threadIdx.x < n) {
+    if (lt < n) {
       long long r;
       bool keep = true;
       if (!overflow) {
-        r = bins[start + c0 + threadIdx.x];
+        r = bins[start + c0 + lt];
       } else {
-        r = tb + c0 + threadIdx.x;
+        r = tb + c0 + lt;
         const BBox bb = bbox[r];
         keep = bb.x0 <= bb.x1 && bb.x1 >= x0 && bb.x0 < x0 + TW && bb.y1 >= y0 && bb.y0 < y0 + TH;
       }
@@ -436,7 +442,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         o.t = (int)(r - tb);
         o.tneg = 0xFFFFFFFFu - (unsigned)o.t;
       }
-      s_tr[threadIdx.x] = o;
+      s_tr[lt] = o;
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
@@ -458,14 +464,24 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           float e[3];
 #pragma unroll
           for (int k = 0; k < 3; ++k) e[k] = (float)(int)((unsigned)T.u0[k] + (unsigned)off[k]);
-          float a = e[0] * T.q[0];
-          float b = e[1] * T.q[1];
-          float c = e[2] * T.q[2];
+          const float a = e[0] * T.q[0];
+          const float b = e[1] * T.q[1];
+          const float c = e[2] * T.q[2];
           float nq = a + b;
           nq = nq + c;
           const float qk = nq / T.d;
           const unsigned long long k = ((unsigned long long)__float_as_uint(qk) << 32) | T.tneg;
-          best = k > best ? k : best;
+          if (BARY) {
+            if (k > best) {
+              best = k;
+              wa = a;
+              wb = b;
+              wn = nq;
+              own = true;
+            }
+          } else {
+            best = k > best ? k : best;
+          }
         }
       } else {
         const Rec R = rec[tb + __builtin_amdgcn_readfirstlane(t)];
@@ -476,8 +492,23 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         if (inside && covered(E) && T.qb >= best_q) {
           float e[3], d;
           edge_values(R, E, e, d);
-          const unsigned long long k = vis_key(depth_key(R, e, d), t);
-          best = k > best ? k : best;
+          const float a = e[0] * R.q[0];
+          const float b = e[1] * R.q[1];
+          const float c = e[2] * R.q[2];
+          float nq = a + b;
+          nq = nq + c;
+          const unsigned long long k = vis_key(nq / d, t);
+          if (BARY) {
+            if (k > best) {
+              best = k;
+              wa = a;
+              wb = b;
+              wn = nq;
+              own = true;
+            }
+          } else {
+            best = k > best ? k : best;
+          }
         }
       }
     }
@@ -487,12 +518,14 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const int t = key_tri(best);
   tri_id[p] = t;
   if (depth) depth[p] = t >= 0 ? 1.0f / key_q(best) : 0.0f;
-  if (bary) {
+  if (BARY) {
     float b0 = 0.f, b1 = 0.f;
     if (t >= 0) {
-      const PixBary pb = pixel_bary(snap_triangle<false>(v, vw, tri_row(tri, vw, (int)t)), px, py);
-      b0 = pb.b[0];
-      b1 = pb.b[1];
+      // a winner from the small-triangle pass: the same products from its vertices
+      if (!own) resolve_products(snap_triangle(v, vw, tri_row(tri, vw, t)), px, py, wa, wb, wn);
+      const float r = __builtin_amdgcn_rcpf(wn);
+      b0 = wa * r;
+      b1 = wb * r;
     }
     bary[2 * p] = b0;
     bary[2 * p + 1] = b1;
@@ -520,7 +553,10 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, twl, thl, tri_base, tile_base, status);
   const long long nt = P->total_tiles;
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)min((nt + 255) / 256, 4096ll)), dim3(256), 0, st, count, nt);
-  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)min((npx + 255) / 256, 8192ll)), dim3(256), 0, st, key, npx);
+  if (P->small_px > 0)
+    hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)min((npx + 255) / 256, 8192ll)), dim3(256), 0, st, key, npx);
+  else
+    key = nullptr;  // no small-triangle pass: every pixel starts from background
   if (P->total_tris > 0) {
     hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
                        v, tri, tri_base, tile_base, P->total_tris, twl, thl, P->small_px, P->px_begin, rec, bbox, count,
@@ -533,9 +569,17 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
     hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
                        tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, offs, P->bin_cap, bins);
   }
-#define MER_RASTER(TW, TH)                                                                                       \
-  hipLaunchKernelGGL((k_raster<TW, TH>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views, P->n_views, tri_base, \
-                     tile_base, rec, bbox, offs, bins, P->bin_cap, key, P->px_begin, v, tri, tri_id, depth, bary, status)
+#define MER_RASTER(TW, TH)                                                                               \
+  do {                                                                                                   \
+    if (bary)                                                                                            \
+      hipLaunchKernelGGL((k_raster<TW, TH, true>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,      \
+                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
+                         P->px_begin, v, tri, tri_id, depth, bary, status);                              \
+    else                                                                                                 \
+      hipLaunchKernelGGL((k_raster<TW, TH, false>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,     \
+                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
+                         P->px_begin, v, tri, tri_id, depth, bary, status);                              \
+  } while (0)
   if (P->tile_w == 8 && P->tile_h == 8) MER_RASTER(8, 8);
   else if (P->tile_w == 16 && P->tile_h == 16) MER_RASTER(16, 16);
   else if (P->tile_w == 32 && P->tile_h == 8) MER_RASTER(32, 8);

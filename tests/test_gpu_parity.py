@@ -54,6 +54,20 @@ def test_parity_recompute_barycentrics(k):
     compare(run_gpu(s, g, store_bary=False), ref, bary=False)
 
 
+@pytest.mark.parametrize("k", [2, 4])
+@pytest.mark.parametrize("small_px", [-1, 16, 4096])
+def test_recomputed_barycentrics_equal_stored(k, small_px):
+    """mer_interpolate with bary = NULL recomputes the barycentrics exactly as
+    the rasterizer's resolve computes them, whichever pass found the winner:
+    the interpolated images are bit-identical."""
+    s, g, _ = case(k)
+    say(f"[parity] stored vs recomputed barycentrics config {k} small_px {small_px}")
+    a = run_gpu(s, g, small_px=small_px)
+    b = run_gpu(s, g, small_px=small_px, store_bary=False)
+    assert np.array_equal(a["tri_id"], b["tri_id"])
+    assert np.array_equal(a["interp"], b["interp"])
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_parity_separate_calls(k):
     s, g, ref = case(k)
