@@ -63,8 +63,10 @@ typedef struct mer_view {
   int32_t n_v, n_t, H, W;
 } mer_view;       /* 48 bytes, no padding */
 
-/* Tile shape (pixels), bin pool capacity (triangle-tile entries; 0 picks a
- * default from the triangle and tile counts) and the small-triangle limit:
+/* Tile shape (pixels), bin pool capacity (triangle-tile entries, at most
+ * INT_MAX - 1; 0 picks a default from the triangle and tile counts; tiles
+ * whose entries do not fit are rasterized by a slower path that scans every
+ * triangle of their view) and the small-triangle limit:
  * a triangle whose box of pixel centres holds at most small_px centres is
  * rasterized by its set-up thread directly into the per-pixel z-buffer key
  * instead of being binned (0 picks the default 16, a negative value bins

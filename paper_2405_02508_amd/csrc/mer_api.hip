@@ -58,7 +58,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   P->total_btiles = btiles;
   P->total_px = px_end;
   int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 16 * tris + 16 * tiles + 4096;
-  if (cap > INT_MAX) cap = INT_MAX;
+  if (cap > INT_MAX - 1) cap = INT_MAX - 1;  // a saturated bin offset (INT_MAX) always overflows
   P->bin_cap = cap;
   P->small_px = (tun && tun->small_px != 0) ? (tun->small_px < 0 ? 0 : tun->small_px) : 16;
   P->n_part = (tiles + 1023) / 1024;
@@ -74,7 +74,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   P->off_offs = off;
   off = align256(off + (tiles + 1) * 4);
   P->off_part = off;
-  off = align256(off + P->n_part * 4);
+  off = align256(off + P->n_part * 8);
   P->off_bins = off;
   off = align256(off + cap * 4);
   P->off_status = off;

@@ -207,54 +207,58 @@ __global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict_
 }
 
 // ----------------------------------------------------------------- scan
-// Exclusive scan of count[0..n) into offs[0..n], offs[n] = total.  Blocks of
+// Exclusive scan of count[0..n) into offs[0..n], offs[n] = total, in 64-bit
+// with offsets saturated at INT_MAX: the bin pool is smaller than that, so a
+// tile whose range does not fit takes the raster's overflow path.  Blocks of
 // 256 threads x 4 items.
-__device__ __forceinline__ int wave_incl_scan(int x) {
+__device__ __forceinline__ long long wave_incl_scan(long long x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
+    const long long y = __shfl_up(x, o, 64);
     if (lane >= o) x += y;
   }
   return x;
 }
 
-__device__ __forceinline__ int block_excl_scan_256(int x, int* s_wave, int& total) {
+__device__ __forceinline__ long long block_excl_scan_256(long long x, long long* s_wave, long long& total) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  int inc = wave_incl_scan(x);
+  const long long inc = wave_incl_scan(x);
   if (lane == 63) s_wave[w] = inc;
   __syncthreads();
-  int pre = 0;
+  long long pre = 0;
   for (int i = 0; i < w; ++i) pre += s_wave[i];
   total = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
   __syncthreads();
   return pre + inc - x;
 }
 
+__device__ __forceinline__ int sat_int(long long x) { return x > 2147483647ll ? 2147483647 : (int)x; }
+
 __global__ void __launch_bounds__(256) k_scan_partial(const int* __restrict__ count, long long n,
-                                                      int* __restrict__ part) {
-  __shared__ int s_wave[4];
+                                                      long long* __restrict__ part) {
+  __shared__ long long s_wave[4];
   const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
-  int s = 0;
+  long long s = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j)
     if (base + j < n) s += count[base + j];
-  int total;
+  long long total;
   block_excl_scan_256(s, s_wave, total);
   if (threadIdx.x == 0) part[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(256) k_scan_parts(int* __restrict__ part, long long n_part) {
-  __shared__ int s_wave[4];
-  __shared__ int s_carry;
+__global__ void __launch_bounds__(256) k_scan_parts(long long* __restrict__ part, long long n_part) {
+  __shared__ long long s_wave[4];
+  __shared__ long long s_carry;
   if (threadIdx.x == 0) s_carry = 0;
   __syncthreads();
   for (long long b = 0; b < n_part; b += 256) {
     const long long i = b + threadIdx.x;
-    int x = i < n_part ? part[i] : 0;
-    int total;
-    int ex = block_excl_scan_256(x, s_wave, total);
-    const int carry = s_carry;
+    const long long x = i < n_part ? part[i] : 0;
+    long long total;
+    const long long ex = block_excl_scan_256(x, s_wave, total);
+    const long long carry = s_carry;
     if (i < n_part) part[i] = carry + ex;
     __syncthreads();
     if (threadIdx.x == 0) s_carry = carry + total;
@@ -263,24 +267,25 @@ __global__ void __launch_bounds__(256) k_scan_parts(int* __restrict__ part, long
 }
 
 __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ count, long long n,
-                                                    const int* __restrict__ part, int* __restrict__ offs,
+                                                    const long long* __restrict__ part, int* __restrict__ offs,
                                                     long long* __restrict__ status) {
-  __shared__ int s_wave[4];
+  __shared__ long long s_wave[4];
   const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
-  int c[4], s = 0;
+  int c[4];
+  long long s = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     c[j] = base + j < n ? count[base + j] : 0;
     s += c[j];
   }
-  int total;
-  int ex = block_excl_scan_256(s, s_wave, total) + part[blockIdx.x];
+  long long total;
+  long long ex = block_excl_scan_256(s, s_wave, total) + part[blockIdx.x];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (base + j < n) offs[base + j] = ex;
+    if (base + j < n) offs[base + j] = sat_int(ex);
     ex += c[j];
     if (base + j == n - 1) {
-      offs[n] = ex;
+      offs[n] = sat_int(ex);
       status[2] = ex;
     }
   }
@@ -298,7 +303,7 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
                                               const BBox* __restrict__ bbox,
                                               int* __restrict__ count, const int* __restrict__ offs,
                                               long long bin_cap, int* __restrict__ bins) {
-  __shared__ int s_tkey[kBinSlots], s_tcnt[kBinSlots], s_nocc;
+  __shared__ int s_tkey[kBinSlots], s_tcnt[kBinSlots], s_toff[kBinSlots], s_nocc;
   clear_tile_table(s_tkey, s_tcnt, &s_nocc);
   __syncthreads();
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -323,7 +328,8 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
     const int gt = s_tkey[i];
     if (gt >= 0) {
       const int n = s_tcnt[i];
-      s_tcnt[i] = offs[gt] + atomicSub(count + gt, n) - n;  // first position of this workgroup's range
+      s_toff[i] = offs[gt];
+      s_tcnt[i] = atomicSub(count + gt, n) - n;  // this workgroup's range within the tile
     }
   }
   __syncthreads();
@@ -332,7 +338,7 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
     // workgroup's range, any other tile its own global counter
     for_each_tile(R, bb, vw, base, tw_log2, th_log2, [&](int gt) {
       const int sl = tile_slot<false>(s_tkey, &s_nocc, gt);
-      const long long pos = sl >= 0 ? (long long)atomicAdd(&s_tcnt[sl], 1)
+      const long long pos = sl >= 0 ? (long long)s_toff[sl] + atomicAdd(&s_tcnt[sl], 1)
                                     : (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
       if (pos < bin_cap) bins[pos] = (int)g;
     });
@@ -543,7 +549,7 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   BBox* bbox = (BBox*)(w + P->off_bbox);
   int* count = (int*)(w + P->off_count);
   int* offs = (int*)(w + P->off_offs);
-  int* part = (int*)(w + P->off_part);
+  long long* part = (long long*)(w + P->off_part);
   int* bins = (int*)(w + P->off_bins);
   long long* status = (long long*)(w + P->off_status);
   unsigned long long* key = (unsigned long long*)(w + P->off_key);

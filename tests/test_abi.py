@@ -75,6 +75,8 @@ def test_plan_totals_and_layout(L):
     assert P.ws_bytes - P.off_key >= 8 * P.total_px
     P2 = mer.plan_init(V, (16, 16), bin_cap=5)
     assert P2.bin_cap == 5 and P2.total_tiles == 2 * 3 + 1
+    # bin offsets are 32-bit and saturate at INT_MAX, so the pool stays below it
+    assert mer.plan_init(V, (8, 8), bin_cap=1 << 40).bin_cap == 2**31 - 2
 
 
 @pytest.mark.parametrize("bad", [
