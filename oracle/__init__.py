@@ -56,6 +56,7 @@ def lib():
         L.orc_interpolate.argtypes = [P, i, P, i, P, i, i, P, i, P]
         L.orc_interpolate_bwd.argtypes = [P, i, P, i, P, i, i, P, i, P, P, P]
         L.orc_edge_grad.argtypes = [P, i, P, i, i, P, P, P, i, i, P, P, P]
+        L.orc_backface.argtypes = [P, i, P, i, i, i, P, P]
         _lib = L
     return _lib
 
@@ -102,6 +103,15 @@ def cover_count(v, tri, H, W):
 def cover_query(v, tri, t, px, py):
     v, tri = _f32(v), _i32(tri)
     return bool(lib().orc_cover_query(_p(v), v.shape[0], _p(tri), int(t), int(px), int(py)))
+
+
+def backface(v, tri, H, W, tri_id):
+    """1.0 where the visible triangle shows its back side (snapped D > 0 with
+    pixel y down), else 0.0; f64 [H*W]."""
+    v, tri, tid = _f32(v), _i32(tri), _i32(tri_id)
+    out = np.zeros(H * W)
+    lib().orc_backface(_p(v), v.shape[0], _p(tri), tri.shape[0], H, W, _p(tid), _p(out))
+    return out
 
 
 def resolve(v, tri, H, W, tri_id):
@@ -162,11 +172,12 @@ def forward(scene, views=None):
     """Per-pixel outputs over all views, packed like the GPU buffers.
 
     Returns dict: tri_id i32 [n_px], depth f64 [n_px], bary f64 [n_px,3],
-    interp f64 [n_px, C_out], image f64 [n_px, C_e] (interp + optional mask).
+    interp f64 [n_px, C_out], image f64 [n_px, C_e] (interp + optional mask),
+    backface f64 [n_px] (1 where the visible triangle shows its back side).
     """
     n_px = scene.n_px
     out = dict(tri_id=np.full(n_px, -1, np.int32), depth=np.zeros(n_px), bary=np.zeros((n_px, 3)),
-               interp=np.zeros((n_px, scene.C_out)), image=np.zeros((n_px, scene.C_e)))
+               interp=np.zeros((n_px, scene.C_out)), image=np.zeros((n_px, scene.C_e)), backface=np.zeros(n_px))
     for i in (range(scene.n_views) if views is None else views):
         vw, vs, ts, ats = _view_slices(scene, i)
         H, W, o = vw["H"], vw["W"], vw["px_off"]
@@ -178,6 +189,7 @@ def forward(scene, views=None):
         out["depth"][sl] = d
         out["bary"][sl] = b
         out["interp"][sl] = it
+        out["backface"][sl] = backface(vs, ts, H, W, tid)
         out["image"][sl, :scene.C_out] = it
         if scene.mask_channel:
             out["image"][sl, scene.C_out] = (tid >= 0).astype(np.float64)

@@ -265,6 +265,26 @@ void orc_resolve(const float *v, int n_v, const int32_t *tri, int H, int W, cons
     }
 }
 
+/* ---------------------------------------------------------- back faces */
+/* out[H*W]: 1 where the visible triangle shows its back side, else 0
+ * (supplement, "Implementation detail": the image that is 1 where the wrong
+ * side of a triangle is visible, fed through EdgeGrad for the back-face
+ * loss).  Orientation: pixel y points down, so a triangle whose vertices run
+ * counter-clockwise on screen -- the front of a closed mesh wound with
+ * outward normals -- has snapped D < 0; its back shows where D > 0.
+ * Background, and an index that names a triangle that does not snap, give 0. */
+void orc_backface(const float *v, int n_v, const int32_t *tri, int n_t, int H, int W, const int32_t *tri_id,
+                  double *out) {
+  orc_tri T;
+  for (int64_t p = 0; p < (int64_t)H * W; ++p) {
+    int t = tri_id[p];
+    out[p] = 0.0;
+    if (t < 0 || t >= n_t) continue;
+    orc_setup(v, n_v, tri, t, &T);
+    if (T.ok && T.D > 0) out[p] = 1.0;
+  }
+}
+
 /* --------------------------------------------------------- interpolate */
 /* out[H*W*(C_a+append_z)]: sum_k b_k a_kc over the visible triangle's
  * vertices; optional last channel interpolates the vertices' screen z. */

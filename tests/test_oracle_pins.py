@@ -579,3 +579,47 @@ def test_p11_error_shrinks_with_resolution():
         ana, fd = _fd_vs_oracle(v, t, attr, N, N, dv, 0.5)
         errs.append(abs(ana - fd) / abs(fd))
     assert errs[2] < errs[0] and errs[1] <= errs[0] * 1.05 + 1e-3, errs
+
+
+# --------------------------------------------------------------- P13 back faces
+def _sphere_view(eye, target, nu=6, W=96, fov=60.0, reverse=False):
+    from paper_2405_02508_amd import scenes
+    V, F = scenes.icosphere(nu)
+    # the orientation fact the pins rest on, from 3D geometry alone: every
+    # face normal (right-hand rule) points away from the centre
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    assert np.all((n * V[F].mean(1)).sum(1) > 0)
+    if reverse:
+        F = F[:, [0, 2, 1]]
+    cam = scenes.look_at(eye, target, scenes.focal_from_fov(fov, W), W, W)
+    vs = scenes.project(V, cam)
+    tri = np.ascontiguousarray(F, np.int32)
+    tid = oracle.rasterize(vs, tri, W, W)
+    return vs, tri, tid, W
+
+
+def test_p13_closed_mesh_from_outside_shows_no_back_face():
+    vs, tri, tid, W = _sphere_view([0.3, -0.2, -3.0], [0, 0, 0])
+    assert (tid >= 0).sum() > 1000
+    assert np.all(oracle.backface(vs, tri, W, W, tid) == 0.0)
+
+
+def test_p13_reversed_winding_shows_only_back_faces():
+    vs, tri, tid, W = _sphere_view([0.3, -0.2, -3.0], [0, 0, 0], reverse=True)
+    np.testing.assert_array_equal(oracle.backface(vs, tri, W, W, tid), (tid >= 0).astype(np.float64))
+
+
+def test_p13_camera_inside_sees_the_inner_side():
+    # from the centre every visible triangle is seen from inside the mesh
+    vs, tri, tid, W = _sphere_view([0.0, 0.0, 0.0], [0.2, 0.1, 1.0], fov=70.0)
+    assert np.all(tid >= 0)
+    assert np.all(oracle.backface(vs, tri, W, W, tid) == 1.0)
+
+
+def test_p13_mirrored_image_swaps_sides():
+    # reflecting the screen x axis reverses every on-screen winding
+    vs, tri, tid, W = _sphere_view([0.3, -0.2, -3.0], [0, 0, 0])
+    vm = vs.copy()
+    vm[:, 0] = W - vm[:, 0]
+    tm = oracle.rasterize(vm, tri, W, W)
+    np.testing.assert_array_equal(oracle.backface(vm, tri, W, W, tm), (tm >= 0).astype(np.float64))
