@@ -126,6 +126,19 @@ int mer_interpolate(const mer_plan *plan, const mer_view *views_dev, const float
                     const float *v, const int32_t *tri, const int32_t *tri_id, const float *bary,
                     int append_z, float *out, void *stream);
 
+/* Back-face image (supplement, "Implementation detail": an image that is 1
+ * where the wrong side of a triangle is visible, passed through EdgeGrad so
+ * that a loss on it moves the geometry).  out[p] = 1.0f where tri_id[p]
+ * names a triangle whose snapped vertices run clockwise on screen as the
+ * viewer sees it, i.e. twice its signed fixed-point area D > 0 with pixel y
+ * pointing down (the front of a closed mesh wound counter-clockwise seen
+ * from outside has D < 0); 0.0f on background, for ids outside [0, n_t)
+ * and for triangles that do not snap (culled).  Pixels in gaps between
+ * views are not written.
+ *   out: float [total_px] (one channel). */
+int mer_backface(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                 const int32_t *tri_id, float *out, void *stream);
+
 /* EdgeGrad backward (Sec. 4.2-4.4): for every horizontal and vertical pair of
  * neighbouring pixels inside a view whose triangle ids differ,
  *   dL/dp = 1/2 sum_c (g[A,c] + g[B,c]) (img[A,c] - img[B,c])

@@ -41,6 +41,15 @@ class Renderer:
         return tid, depth, bary
 
 
+    def backface(self, v, tid):
+        """Back-face image [n_px, 1]: 1 where the visible triangle shows its
+        back side.  A 0/1 image has no gradient of its own; pass it through
+        EdgeGrad (``back_face_image``) so that a loss on it moves the edges."""
+        out = torch.empty(self.n_px, 1, dtype=torch.float32, device=self.device)
+        self.ctx.backface(v.detach().contiguous(), self.tri, tid, out)
+        return out
+
+
 class Interpolate(torch.autograd.Function):
     """out = sum_k b_k attr_k (+ interpolated z); backward: attr and Omega to v."""
 
@@ -138,3 +147,10 @@ def project(v_world, R, C, f, cx, cy):
     x = f[:, None] * pc[..., 0] / z + cx[:, None]
     y = f[:, None] * pc[..., 1] / z + cy[:, None]
     return torch.stack([x, y, z], -1).reshape(-1, 3)
+
+
+def back_face_image(r: Renderer, v, tid, flags: int = 0):
+    """The back-face image with the micro-edge gradient attached: the loss
+    ||image||^2 (supplement, "Implementation detail", back-face loss) then
+    moves the vertices so that fewer back sides show."""
+    return EdgeGrad.apply(r.backface(v, tid), v, tid, r, flags)

@@ -108,6 +108,12 @@ int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* a
                                  (hipStream_t)stream);
 }
 
+int mer_backface(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                 const int32_t* tri_id, float* out, void* stream) {
+  if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !out) return MER_EINVAL;
+  return mer::launch_backface(P, views_dev, v, tri, tri_id, out, (hipStream_t)stream);
+}
+
 int mer_edge_grad(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
                   const int32_t* tri_id, const float* img, const float* g_img, int C_e, int flags, float* g_v,
                   void* ws, void* stream) {

@@ -97,6 +97,38 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
   for (long long i = threadIdx.x; i < n_here * C; i += blockDim.x) dst[i] = s_out[i];
 }
 
+// ------------------------------------------------------------- back faces
+// One thread per pixel: 1 where the visible triangle's snapped signed area
+// is positive (its back side faces the viewer), else 0.
+__global__ void __launch_bounds__(256) k_backface(const mer_view* __restrict__ views, int n_views,
+                                                  const float* __restrict__ v, const int32_t* __restrict__ tri,
+                                                  const int32_t* __restrict__ tri_id, float* __restrict__ out,
+                                                  long long px_begin, long long total_px) {
+  const long long p = px_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int wvi = wave_view(views, n_views, p - (threadIdx.x & 63));
+  if (p >= total_px) return;
+  int vi = wvi;
+  if (vi + 1 < n_views && p >= views[vi + 1].px_off) vi = find_view_px(views, n_views, p);
+  const mer_view vw = views[vi];
+  const long long local = p - vw.px_off;
+  if (local < 0 || local >= (long long)vw.H * vw.W) return;  // gap between views
+  const int t = tri_id[p];
+  float r = 0.f;
+  if (t >= 0 && t < vw.n_t) {
+    const Snap sn = snap_triangle<false>(v, vw, tri_row(tri, vw, t));
+    r = sn.ok && sn.D > 0 ? 1.f : 0.f;
+  }
+  out[p] = r;
+}
+
+int launch_backface(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
+                    const int32_t* tri_id, float* out, hipStream_t st) {
+  const long long n = P->total_px - P->px_begin;
+  hipLaunchKernelGGL(k_backface, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views, v, tri,
+                     tri_id, out, P->px_begin, P->total_px);
+  return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
+}
+
 // ------------------------------------------------------------- backward
 template <bool EXACT_Q>
 __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, const mer_view& vw, int t) {

@@ -10,6 +10,8 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
 int launch_interpolate(const mer_plan* P, const mer_view* views, const float* attr, int C_a, const float* v,
                        const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
                        hipStream_t st);
+int launch_backface(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
+                    const int32_t* tri_id, float* out, hipStream_t st);
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
                     const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, void* ws,

@@ -19,8 +19,8 @@ NO_INTERSECT = 1
 SKIP_EDGE = 2
 SKIP_INTERP = 4
 
-SYMBOLS = ("mer_plan_init", "mer_rasterize", "mer_interpolate", "mer_edge_grad", "mer_interpolate_bwd",
-           "mer_backward_fused", "mer_status", "mer_strerror", "mer_version")
+SYMBOLS = ("mer_plan_init", "mer_rasterize", "mer_interpolate", "mer_backface", "mer_edge_grad",
+           "mer_interpolate_bwd", "mer_backward_fused", "mer_status", "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -63,6 +63,7 @@ def lib():
         L.mer_plan_init.argtypes = [ctypes.POINTER(View), i, ctypes.POINTER(Tuning), ctypes.POINTER(Plan)]
         L.mer_rasterize.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, P]
         L.mer_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, P, i, P, P]
+        L.mer_backface.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P]
         L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P, P]
         L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P, P]
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
@@ -195,6 +196,17 @@ class Context:
                                      _stream()))
 
     # backward -------------------------------------------------------------
+    def backface(self, v, tri, tri_id, out):
+        """out[p] = 1 where the visible triangle shows its back side, else 0."""
+        import torch
+        _need(out, torch.float32, "out")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri)
+        self._px(tri_id, "tri_id")
+        self._px(out, "out")
+        _check(lib().mer_backface(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
+                                  _ptr(out), _stream()))
+
     def edge_grad(self, v, tri, tri_id, img, g_img, g_v, flags=0):
         import torch
         _need(img, torch.float32, "img")

@@ -117,6 +117,8 @@ def test_calls_reject_null_arguments_before_any_launch(L):
     assert L.mer_rasterize(p, fake, fake, fake, fake, None, None, None, None) == -2
     assert L.mer_interpolate(p, fake, fake, 0, fake, fake, fake, fake, 0, fake, None) == -1
     assert L.mer_interpolate(p, fake, fake, 64, fake, fake, fake, fake, 1, fake, None) == -1
+    assert L.mer_backface(p, fake, fake, fake, fake, None, None) == -1
+    assert L.mer_backface(p, None, fake, fake, fake, fake, None) == -1
     assert L.mer_edge_grad(p, fake, fake, fake, fake, fake, fake, 0, 0, fake, fake, None) == -1
     assert L.mer_edge_grad(p, fake, fake, fake, fake, fake, fake, 3, 0, fake, None, None) == -2
     assert L.mer_interpolate_bwd(p, fake, fake, 3, fake, fake, fake, 0, fake, 2, fake, fake, fake, None) == -1
