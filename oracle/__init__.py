@@ -241,3 +241,46 @@ def step_view(scene, i, target_value=0.5):
     interpolate_bwd(ats, vs, ts, H, W, tid, np.ascontiguousarray(g[:, :scene.C_out]), scene.append_z,
                     g_attr=ga, g_v=gv)
     return H * W
+
+
+# ------------------------------------------------ vertex transform (numpy)
+# Supplement, "Implementation detail": the vertex transform module takes the
+# vertices to the camera frame and projects them onto the image plane; its
+# backward pass is the derivative of that map.  Camera: rows of R are the
+# camera axes in world coordinates (x right, y down, z forward), C the centre,
+# f the focal length and (cx, cy) the principal point in pixels.  View i maps
+# world rows w_off[i] .. w_off[i] + n_v to screen rows v_off .. v_off + n_v.
+def transform(v_world, R, C, f, cx, cy, w_off, views):
+    """Screen vertices (x_px, y_px, z) [sum n_v, 3], binary64."""
+    V = np.asarray(views, np.int64)
+    vw = np.asarray(v_world, np.float64)
+    out = np.zeros((max([int(r[0] + r[4]) for r in V] + [0]), 3))
+    for i, r in enumerate(V):
+        v_off, n_v = int(r[0]), int(r[4])
+        pw = vw[int(w_off[i]): int(w_off[i]) + n_v]
+        pc = (pw - np.asarray(C[i], np.float64)) @ np.asarray(R[i], np.float64).T  # camera frame
+        z = pc[:, 2]
+        out[v_off: v_off + n_v, 0] = f[i] * pc[:, 0] / z + cx[i]
+        out[v_off: v_off + n_v, 1] = f[i] * pc[:, 1] / z + cy[i]
+        out[v_off: v_off + n_v, 2] = z
+    return out
+
+
+def transform_bwd(v_world, R, C, f, cx, cy, w_off, views, g_screen):
+    """dL/d(world vertices) [n_world, 3]: for every view and vertex, the
+    transpose of the projection's Jacobian applied to dL/d(screen vertex),
+    summed over the views that use the vertex.  binary64."""
+    V = np.asarray(views, np.int64)
+    vw = np.asarray(v_world, np.float64)
+    gs = np.asarray(g_screen, np.float64)
+    g = np.zeros_like(vw)
+    for i, r in enumerate(V):
+        v_off, n_v = int(r[0]), int(r[4])
+        Ri = np.asarray(R[i], np.float64)
+        pc = (vw[int(w_off[i]): int(w_off[i]) + n_v] - np.asarray(C[i], np.float64)) @ Ri.T
+        x, y, z = pc[:, 0], pc[:, 1], pc[:, 2]
+        gx, gy, gz = gs[v_off: v_off + n_v, 0], gs[v_off: v_off + n_v, 1], gs[v_off: v_off + n_v, 2]
+        # d(screen)/d(camera frame): x_px = f x / z + cx, y_px = f y / z + cy, z_out = z
+        g_cam = np.stack([gx * f[i] / z, gy * f[i] / z, gz - gx * f[i] * x / (z * z) - gy * f[i] * y / (z * z)], 1)
+        g[int(w_off[i]): int(w_off[i]) + n_v] += g_cam @ Ri  # camera frame = R (world - C)
+    return g

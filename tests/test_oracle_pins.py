@@ -623,3 +623,86 @@ def test_p13_mirrored_image_swaps_sides():
     vm[:, 0] = W - vm[:, 0]
     tm = oracle.rasterize(vm, tri, W, W)
     np.testing.assert_array_equal(oracle.backface(vm, tri, W, W, tm), (tm >= 0).astype(np.float64))
+
+
+# ----------------------------------------------------- P14 vertex transform
+def _cams(n, seed):
+    rng = np.random.default_rng(seed)
+    R, C = [], []
+    for _ in range(n):
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        R.append(q * np.sign(np.linalg.det(q)))  # a rotation
+        C.append(rng.normal(size=3) * 2.0)
+    f = rng.uniform(300, 900, n)
+    cx, cy = rng.uniform(100, 300, n), rng.uniform(100, 300, n)
+    return np.array(R), np.array(C), f, cx, cy
+
+
+def _views_for(n_views, n_v):
+    return np.array([[i * n_v, 0, 0, 0, n_v, 0, 8, 8] for i in range(n_views)], np.int64)
+
+
+def _points_in_front(R, C, n, seed):
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(2.0, 5.0, n)
+    u = rng.uniform(-0.4, 0.4, (n, 2))
+    return C + d[:, None] * (R[2] + u[:, :1] * R[0] + u[:, 1:] * R[1])
+
+
+def test_p14_principal_ray_lands_on_the_principal_point():
+    R, C, f, cx, cy = _cams(3, 1)
+    for i in range(3):
+        d = np.array([0.5, 2.0, 7.0])
+        pts = C[i] + d[:, None] * R[i][2]
+        out = oracle.transform(pts, R[i:i + 1], C[i:i + 1], f[i:i + 1], cx[i:i + 1], cy[i:i + 1], [0],
+                               _views_for(1, 3))
+        np.testing.assert_allclose(out, np.stack([np.full(3, cx[i]), np.full(3, cy[i]), d], 1), rtol=0, atol=1e-12)
+
+
+def test_p14_rigid_motion_of_world_and_camera_changes_nothing():
+    R, C, f, cx, cy = _cams(2, 2)
+    pts = _points_in_front(R[0], C[0], 50, 3)
+    Q, _ = np.linalg.qr(np.random.default_rng(4).normal(size=(3, 3)))
+    Q = Q * np.sign(np.linalg.det(Q))
+    T = np.array([0.3, -1.2, 2.0])
+    a = oracle.transform(pts, R[:1], C[:1], f[:1], cx[:1], cy[:1], [0], _views_for(1, 50))
+    b = oracle.transform(pts @ Q.T + T, [R[0] @ Q.T], [Q @ C[0] + T], f[:1], cx[:1], cy[:1], [0], _views_for(1, 50))
+    np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-9)
+
+
+def test_p14_points_on_one_ray_share_a_pixel():
+    R, C, f, cx, cy = _cams(1, 5)
+    p = _points_in_front(R[0], C[0], 20, 6)
+    s = np.random.default_rng(7).uniform(0.5, 3.0, 20)
+    q = C[0] + s[:, None] * (p - C[0])
+    a = oracle.transform(p, R, C, f, cx, cy, [0], _views_for(1, 20))
+    b = oracle.transform(q, R, C, f, cx, cy, [0], _views_for(1, 20))
+    np.testing.assert_allclose(b[:, :2], a[:, :2], rtol=1e-12, atol=1e-9)
+    np.testing.assert_allclose(b[:, 2], s * a[:, 2], rtol=1e-12)
+
+
+def test_p14_backward_matches_central_differences_and_sums_views():
+    R, C, f, cx, cy = _cams(3, 8)
+    n = 12
+    pts = _points_in_front(R[0], C[0], n, 9)
+    # three views of the same world rows (screen rows of view i at i * n)
+    for i in (1, 2):
+        R[i], C[i] = R[0] @ np.array([[1, 0, 0], [0, np.cos(0.1 * i), -np.sin(0.1 * i)],
+                                      [0, np.sin(0.1 * i), np.cos(0.1 * i)]]), C[0] + 0.05 * i
+    V = _views_for(3, n)
+    w_off = [0, 0, 0]
+    g = np.random.default_rng(10).normal(size=(3 * n, 3))
+    got = oracle.transform_bwd(pts, R, C, f, cx, cy, w_off, V, g)
+    h = 1e-6
+    fd = np.zeros_like(pts)
+    for j in range(n):
+        for a in range(3):
+            dp = np.zeros_like(pts)
+            dp[j, a] = h
+            fp = oracle.transform(pts + dp, R, C, f, cx, cy, w_off, V)
+            fm = oracle.transform(pts - dp, R, C, f, cx, cy, w_off, V)
+            fd[j, a] = ((fp - fm) / (2 * h) * g).sum()
+    np.testing.assert_allclose(got, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+    per_view = sum(oracle.transform_bwd(pts, R[i:i + 1], C[i:i + 1], f[i:i + 1], cx[i:i + 1], cy[i:i + 1], [0],
+                                        _views_for(1, n), g[i * n:(i + 1) * n]) for i in range(3))
+    np.testing.assert_allclose(got, per_view, rtol=1e-12, atol=1e-12)
