@@ -88,7 +88,21 @@ typedef struct mer_plan {
   int64_t off_viewtab, off_rec, off_bbox, off_count, off_offs, off_part, off_bins, off_status, off_key;
   int64_t n_part;
   int64_t total_btiles, off_bviewtab; /* 16x16 tiles of the backward sweep */
+  int64_t total_v, off_vbase;         /* screen vertices over all views, their per-view prefix */
 } mer_plan;
+
+/* One pinhole camera per view for the vertex transform: the rows of R are
+ * the camera axes in world coordinates (x right, y down, z forward), C the
+ * camera centre, f the focal length and (cx, cy) the principal point in
+ * pixels.  The view's n_v screen rows v_off .. v_off + n_v - 1 are its world
+ * rows w_off .. w_off + n_v - 1 (views of one mesh share w_off). */
+typedef struct mer_camera {
+  float R[9];       /* row-major */
+  float C[3];
+  float f, cx, cy;
+  int32_t reserved; /* set to 0 */
+  int64_t w_off;
+} mer_camera;       /* 72 bytes */
 
 /* Validate the host copy of the view table (H, W in [1, 32767], n_v, n_t >= 0,
  * offsets >= 0, views packed in order; sum n_t <= INT_MAX and fewer than
@@ -97,6 +111,23 @@ typedef struct mer_plan {
  * Reads host memory only.  MER_EINVAL on a bad view, MER_ETUNING on an
  * unsupported tile shape. */
 int mer_plan_init(const mer_view *views_host, int n_views, const mer_tuning *tun, mer_plan *plan);
+
+/* Vertex transform module (supplement, "Implementation detail": vertices
+ * to the camera frame, then projected onto the image plane).  For view i and
+ * j < n_v, with p = R (v_world[w_off + j] - C) in binary32 (no fused
+ * multiply-add): v_screen[v_off + j] = (f p_x / p_z + cx, f p_y / p_z + cy, p_z).
+ * A vertex behind the camera gets p_z <= 0 and is culled by the rasterizer.
+ *   cams_dev: device copy of n_views mer_camera.  v_world: float [*, 3], at
+ *   least max_i(w_off + n_v) rows.  v_screen: float [*, 3] rows as the view
+ *   table lays them out.  ws: the plan's workspace. */
+int mer_transform(const mer_plan *plan, const mer_view *views_dev, const mer_camera *cams_dev, const float *v_world,
+                  float *v_screen, void *ws, void *stream);
+
+/* Backward of mer_transform (the derivative of the forward map):
+ * g_world[w_off + j] += J^T g_screen[v_off + j] with J = d(v_screen)/d(v_world)
+ * at the vertex, summed over every view that uses the vertex (float atomics). */
+int mer_transform_bwd(const mer_plan *plan, const mer_view *views_dev, const mer_camera *cams_dev,
+                      const float *v_world, const float *g_screen, float *g_world, void *ws, void *stream);
 
 /* Rasterization module + barycentrics (supplement, "Rasterization module",
  * "Barycentrics module"; the z-buffer of the Rasterization module).

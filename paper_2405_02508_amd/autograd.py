@@ -8,9 +8,10 @@ pass.  ``RenderStep`` fuses all three for one call per optimisation step:
 its forward rasterizes and interpolates every view, its backward runs the
 fused micro-edge + interpolation sweep once.
 
-Screen vertices are per view (rows v_off .. v_off + n_v of ``v``); a world
-to screen transform written with torch ops in front of these functions
-reduces the per-view screen gradients to world space through autograd.
+Screen vertices are per view (rows v_off .. v_off + n_v of ``v``).
+``Transform`` (the vertex transform module) makes them from world vertices
+and one pinhole camera per view, and its backward reduces the per-view
+screen gradients to world space; ``project`` does the same with torch ops.
 """
 from __future__ import annotations
 
@@ -48,6 +49,29 @@ class Renderer:
         out = torch.empty(self.n_px, 1, dtype=torch.float32, device=self.device)
         self.ctx.backface(v.detach().contiguous(), self.tri, tid, out)
         return out
+
+
+class Transform(torch.autograd.Function):
+    """World vertices -> screen vertices of every view (supplement,
+    "Implementation detail", vertex transform module); backward: the
+    transposed Jacobian of the projection, summed over the views."""
+
+    @staticmethod
+    def forward(ctx, v_world, cams: mer.Cameras, r: Renderer):
+        vw = v_world.detach().contiguous()
+        v = torch.zeros(r.ctx.need_v, 3, dtype=torch.float32, device=v_world.device)
+        r.ctx.transform(cams, vw, v)
+        ctx.save_for_backward(vw)
+        ctx.cams = cams
+        ctx.r = r
+        return v
+
+    @staticmethod
+    def backward(ctx, g_v):
+        (vw,) = ctx.saved_tensors
+        g_world = torch.zeros_like(vw)
+        ctx.r.ctx.transform_bwd(ctx.cams, vw, g_v.contiguous(), g_world)
+        return g_world, None, None
 
 
 class Interpolate(torch.autograd.Function):

@@ -37,7 +37,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   const int tw = tun ? tun->tile_w : 8, th = tun ? tun->tile_h : 8;
   if (!tile_supported(tw, th)) return MER_ETUNING;
   memset(P, 0, sizeof(*P));
-  int64_t tris = 0, tiles = 0, btiles = 0, px_end = 0;
+  int64_t tris = 0, tiles = 0, btiles = 0, px_end = 0, verts = 0;
   for (int i = 0; i < n_views; ++i) {
     const mer_view& w = views[i];
     if (w.H < 1 || w.W < 1 || w.H > 32767 || w.W > 32767) return MER_EINVAL;
@@ -45,6 +45,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
     if (w.px_off < px_end) return MER_EINVAL;  // views packed in order, no overlap
     px_end = w.px_off + (int64_t)w.H * w.W;
     tris += w.n_t;
+    verts += w.n_v;
     tiles += (int64_t)((w.W + tw - 1) / tw) * ((w.H + th - 1) / th);
     btiles += (int64_t)((w.W + 15) / 16) * ((w.H + 15) / 16);
   }
@@ -57,6 +58,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   P->total_tiles = tiles;
   P->total_btiles = btiles;
   P->total_px = px_end;
+  P->total_v = verts;
   int64_t cap = (tun && tun->bin_cap > 0) ? tun->bin_cap : 16 * tris + 16 * tiles + 4096;
   if (cap > INT_MAX - 1) cap = INT_MAX - 1;  // a saturated bin offset (INT_MAX) always overflows
   P->bin_cap = cap;
@@ -83,6 +85,8 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   off = align256(off + (px_end - P->px_begin) * 8);
   P->off_bviewtab = off;
   off = align256(off + 2 * (int64_t)(n_views + 1) * 8);
+  P->off_vbase = off;
+  off = align256(off + (int64_t)(n_views + 1) * 8);
   P->ws_bytes = off;
   return MER_OK;
 }
@@ -106,6 +110,20 @@ int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* a
   if ((append_z || !bary) && !v) return MER_EINVAL;
   return mer::launch_interpolate(P, views_dev, attr, C_a, v, tri, tri_id, bary, append_z ? 1 : 0, out,
                                  (hipStream_t)stream);
+}
+
+int mer_transform(const mer_plan* P, const mer_view* views_dev, const mer_camera* cams_dev, const float* v_world,
+                  float* v_screen, void* ws, void* stream) {
+  if (!plan_ok(P) || !views_dev || !cams_dev || !v_world || !v_screen) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  return mer::launch_transform(P, views_dev, cams_dev, v_world, v_screen, ws, (hipStream_t)stream);
+}
+
+int mer_transform_bwd(const mer_plan* P, const mer_view* views_dev, const mer_camera* cams_dev,
+                      const float* v_world, const float* g_screen, float* g_world, void* ws, void* stream) {
+  if (!plan_ok(P) || !views_dev || !cams_dev || !v_world || !g_screen || !g_world) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  return mer::launch_transform_bwd(P, views_dev, cams_dev, v_world, g_screen, g_world, ws, (hipStream_t)stream);
 }
 
 int mer_backface(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,

@@ -10,6 +10,10 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
 int launch_interpolate(const mer_plan* P, const mer_view* views, const float* attr, int C_a, const float* v,
                        const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
                        hipStream_t st);
+int launch_transform(const mer_plan* P, const mer_view* views, const mer_camera* cams, const float* v_world,
+                     float* v_screen, void* ws, hipStream_t st);
+int launch_transform_bwd(const mer_plan* P, const mer_view* views, const mer_camera* cams, const float* v_world,
+                         const float* g_screen, float* g_world, void* ws, hipStream_t st);
 int launch_backface(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, float* out, hipStream_t st);
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,

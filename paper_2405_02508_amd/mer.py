@@ -19,8 +19,9 @@ NO_INTERSECT = 1
 SKIP_EDGE = 2
 SKIP_INTERP = 4
 
-SYMBOLS = ("mer_plan_init", "mer_rasterize", "mer_interpolate", "mer_backface", "mer_edge_grad",
-           "mer_interpolate_bwd", "mer_backward_fused", "mer_status", "mer_strerror", "mer_version")
+SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_interpolate",
+           "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused", "mer_status",
+           "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -42,7 +43,13 @@ class Plan(ctypes.Structure):
                 ("off_viewtab", ctypes.c_int64), ("off_rec", ctypes.c_int64), ("off_bbox", ctypes.c_int64),
                 ("off_count", ctypes.c_int64), ("off_offs", ctypes.c_int64), ("off_part", ctypes.c_int64),
                 ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("off_key", ctypes.c_int64),
-                ("n_part", ctypes.c_int64), ("total_btiles", ctypes.c_int64), ("off_bviewtab", ctypes.c_int64)]
+                ("n_part", ctypes.c_int64), ("total_btiles", ctypes.c_int64), ("off_bviewtab", ctypes.c_int64),
+                ("total_v", ctypes.c_int64), ("off_vbase", ctypes.c_int64)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_float * 9), ("C", ctypes.c_float * 3), ("f", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("reserved", ctypes.c_int32), ("w_off", ctypes.c_int64)]
 
 
 class MerError(RuntimeError):
@@ -64,6 +71,8 @@ def lib():
         L.mer_rasterize.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, P]
         L.mer_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, P, i, P, P]
         L.mer_backface.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P]
+        L.mer_transform.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P]
+        L.mer_transform_bwd.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P]
         L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P, P]
         L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P, P]
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
@@ -139,6 +148,7 @@ class Context:
         self.need_v = int((V[:, 0] + V[:, 4]).max())
         self.need_t = int((V[:, 1] + V[:, 5]).max())
         self.need_a = int((V[:, 2] + V[:, 4]).max())
+        self.n_views = int(V.shape[0])
 
     def _rows(self, t, n, name, cols=None):
         if t is None:
@@ -196,6 +206,36 @@ class Context:
                                      _stream()))
 
     # backward -------------------------------------------------------------
+    # vertex transform ---------------------------------------------------
+    def transform(self, cams, v_world, v_screen):
+        """Screen vertices of every view from world vertices (``cams``: Cameras)."""
+        import torch
+        _need(v_world, torch.float32, "v_world")
+        _need(v_screen, torch.float32, "v_screen")
+        self._cams(cams, v_world)
+        self._rows(v_screen, self.need_v, "v_screen", 3)
+        _check(lib().mer_transform(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(cams.dev), _ptr(v_world),
+                                   _ptr(v_screen), _ptr(self.ws), _stream()))
+
+    def transform_bwd(self, cams, v_world, g_screen, g_world):
+        """g_world += dL/d(world vertices) from dL/d(screen vertices)."""
+        import torch
+        _need(v_world, torch.float32, "v_world")
+        _need(g_screen, torch.float32, "g_screen")
+        _need(g_world, torch.float32, "g_world")
+        self._rows(g_world, self._cams(cams, v_world), "g_world", 3)
+        self._rows(g_screen, self.need_v, "g_screen", 3)
+        _check(lib().mer_transform_bwd(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(cams.dev),
+                                       _ptr(v_world), _ptr(g_screen), _ptr(g_world), _ptr(self.ws), _stream()))
+
+    def _cams(self, cams, v_world):
+        """Check the camera table against the views; world rows needed."""
+        if cams.n != self.n_views:
+            raise MerError(f"{cams.n} cameras for {self.n_views} views")
+        need = cams.need_for(self.views_i64)
+        self._rows(v_world, need, "v_world", 3)
+        return need
+
     def backface(self, v, tri, tri_id, out):
         """out[p] = 1 where the visible triangle shows its back side, else 0."""
         import torch
@@ -266,3 +306,30 @@ class Context:
         out = (ctypes.c_int64 * 4)()
         _check(lib().mer_status(ctypes.byref(self.plan), _ptr(self.ws), _stream(), out))
         return dict(overflow_tiles=out[0], culled=out[1], entries=out[2], bin_cap=out[3])
+
+
+class Cameras:
+    """Device copy of one pinhole camera per view (mer_camera): rows of R are
+    the camera axes in world coordinates (x right, y down, z forward), C the
+    centre, f the focal length and (cx, cy) the principal point in pixels;
+    view i reads world rows w_off[i] .. w_off[i] + n_v - 1."""
+
+    def __init__(self, views_i64, R, C, f, cx, cy, w_off, device="cuda"):
+        import torch
+        V = np.asarray(views_i64, np.int64)
+        n = V.shape[0]
+        arr = (Camera * n)()
+        R, C = np.asarray(R, np.float64).reshape(n, 9), np.asarray(C, np.float64).reshape(n, 3)
+        for i in range(n):
+            arr[i].R[:] = [float(x) for x in R[i]]
+            arr[i].C[:] = [float(x) for x in C[i]]
+            arr[i].f, arr[i].cx, arr[i].cy = float(f[i]), float(cx[i]), float(cy[i])
+            arr[i].reserved = 0
+            arr[i].w_off = int(w_off[i])
+        self.n = n
+        self.w_off = np.asarray(w_off, np.int64)
+        self.dev = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(device)
+
+    def need_for(self, V):
+        V = np.asarray(V, np.int64)
+        return int(max([int(self.w_off[i] + V[i, 4]) for i in range(V.shape[0])] + [0]))

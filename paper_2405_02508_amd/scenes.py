@@ -247,6 +247,20 @@ def _pack(name, per_view, attr_blocks, append_z, mask_channel, recompute=False,
                  np.asarray(rows, dtype=np.int64), append_z, mask_channel, vt, recompute)
 
 
+def _world(blocks, block_of_view, cams):
+    """World-space form of a scene for the vertex transform: world vertices
+    (f32, the given blocks stacked), one pinhole camera per view (rows of R are
+    the camera axes) and each view's first world row."""
+    offs, acc = [], 0
+    for b in blocks:
+        offs.append(acc)
+        acc += b.shape[0]
+    return dict(v=np.ascontiguousarray(np.concatenate(blocks, 0), dtype=np.float32),
+                R=np.stack([c.R for c in cams]), C=np.stack([c.C for c in cams]),
+                f=np.array([c.f for c in cams]), cx=np.array([c.cx for c in cams]),
+                cy=np.array([c.cy for c in cams]), w_off=np.array([offs[b] for b in block_of_view], np.int64))
+
+
 def _displaced_pair(rng, nu, sigma, shift, second=True, nu2=None):
     """One or two radially displaced unit spheres; the copy is shifted along x."""
     vs, fs = icosphere(nu)
@@ -308,11 +322,14 @@ def make_config(k: int, small: bool = False) -> Scene:
         seg = np.eye(4)[region]
         attr = np.concatenate([rgb, seg], 1).astype(np.float32)
         eyes = fibonacci_sphere(n_cam, 1.0)
-        per, tgt = [], []
+        per, cams = [], []
         for e in eyes:
             cam = look_at(e, [0, 0, 0], f, H, W, cx=W / 2.0, cy=H / 2.0)
             per.append((project(V, cam), fs, 0, 0, H, W))
-        return _pack(f"head-nu{nu}-{n_cam}x{W}x{H}", per, [attr], True, False)
+            cams.append(cam)
+        sc = _pack(f"head-nu{nu}-{n_cam}x{W}x{H}", per, [attr], True, False)
+        sc.meta["world"] = _world([V], [0] * n_cam, cams)
+        return sc
     if k == 4:
         n_scenes = 8 if small else 256
         tmax = 2e4 if small else 2e5
@@ -321,7 +338,7 @@ def make_config(k: int, small: bool = False) -> Scene:
         n_int = max(1, int(round(0.1 * n_scenes)))
         inter = np.zeros(n_scenes, bool)
         inter[rng.choice(n_scenes, n_int, replace=False)] = True
-        per, attrs, tgt = [], [], []
+        per, attrs, tgt, blocks, cams = [], [], [], [], []
         for s in range(n_scenes):
             if inter[s]:
                 nu = max(5, int(round(math.sqrt(T_s[s] / 40.0))))
@@ -337,8 +354,11 @@ def make_config(k: int, small: bool = False) -> Scene:
             vt = V + rng.normal(0, 0.01, size=V.shape)
             per.append((project(V, cam), F, s, s, Hd, Wd))
             tgt.append(project(vt, cam))
+            blocks.append(V)
+            cams.append(cam)
         sc = _pack(f"batched-{n_scenes}-scenes", per, attrs, False, False, target_per_view=tgt)
         sc.meta["intersecting"] = [int(i) for i in np.nonzero(inter)[0]]
+        sc.meta["world"] = _world(blocks, list(range(n_scenes)), cams)
         return sc
     if k == 5:
         nu = 32 if small else 224
@@ -347,12 +367,15 @@ def make_config(k: int, small: bool = False) -> Scene:
         V, F = _displaced_pair(rng, nu, 0.02, 0.3)
         attr = rng.uniform(0, 1, size=(V.shape[0], 8)).astype(np.float32)
         eyes = fibonacci_sphere(n_cam, 3.0, center=(0.15, 0.0, 0.0))
-        per = []
+        per, cams = [], []
         for e in eyes:
             cam = look_at(e, [0.15, 0.0, 0.0], focal_from_fov(45, W), H, W)
             per.append((project(V, cam), F, 0, 0, H, W))
-        return _pack(f"recompute-pair-nu{nu}-{n_cam}x{W}px", per, [attr], False, False,
-                     recompute=True)
+            cams.append(cam)
+        sc = _pack(f"recompute-pair-nu{nu}-{n_cam}x{W}px", per, [attr], False, False,
+                   recompute=True)
+        sc.meta["world"] = _world([V], [0] * n_cam, cams)
+        return sc
     raise ValueError("config index must be 1..5")
 
 

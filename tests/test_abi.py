@@ -43,14 +43,17 @@ def test_library_exports_every_declared_symbol(L):
 def test_struct_layout_matches_header(tmp_path):
     c = tmp_path / "lay.c"
     c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "mer.h"\nint main(void){'
-                 'printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(mer_view), sizeof(mer_tuning), sizeof(mer_plan),'
-                 'offsetof(mer_view,n_v), offsetof(mer_plan,ws_bytes), offsetof(mer_plan,n_part));return 0;}')
+                 'printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mer_view), sizeof(mer_tuning),'
+                 'sizeof(mer_plan), offsetof(mer_view,n_v), offsetof(mer_plan,ws_bytes), offsetof(mer_plan,n_part),'
+                 'sizeof(mer_camera), offsetof(mer_camera,f), offsetof(mer_camera,w_off));return 0;}')
     exe = tmp_path / "lay"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = [ctypes.sizeof(mer.View), ctypes.sizeof(mer.Tuning), ctypes.sizeof(mer.Plan),
-            mer.View.n_v.offset, mer.Plan.ws_bytes.offset, mer.Plan.n_part.offset]
+            mer.View.n_v.offset, mer.Plan.ws_bytes.offset, mer.Plan.n_part.offset,
+            ctypes.sizeof(mer.Camera), mer.Camera.f.offset, mer.Camera.w_off.offset]
     assert got == want
+    assert want[6] == 72
 
 
 def test_version_and_strerror(L):
@@ -117,6 +120,10 @@ def test_calls_reject_null_arguments_before_any_launch(L):
     assert L.mer_rasterize(p, fake, fake, fake, fake, None, None, None, None) == -2
     assert L.mer_interpolate(p, fake, fake, 0, fake, fake, fake, fake, 0, fake, None) == -1
     assert L.mer_interpolate(p, fake, fake, 64, fake, fake, fake, fake, 1, fake, None) == -1
+    assert L.mer_transform(p, fake, None, fake, fake, fake, None) == -1
+    assert L.mer_transform(p, fake, fake, fake, fake, None, None) == -2
+    assert L.mer_transform_bwd(p, fake, fake, fake, fake, None, fake, None) == -1
+    assert L.mer_transform_bwd(p, fake, fake, fake, fake, fake, None, None) == -2
     assert L.mer_backface(p, fake, fake, fake, fake, None, None) == -1
     assert L.mer_backface(p, None, fake, fake, fake, fake, None) == -1
     assert L.mer_edge_grad(p, fake, fake, fake, fake, fake, fake, 0, 0, fake, fake, None) == -1

@@ -1,0 +1,79 @@
+"""GPU vertex transform (world -> per-view screen vertices) and its backward
+against the oracle, alone and inside an autograd step."""
+import dataclasses
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_02508_amd import mer, scenes
+from tests.gpu_util import rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=None)
+def scene(k):
+    return scenes.make_config(k, small=True)
+
+
+def cams_of(s):
+    w = s.meta["world"]
+    return mer.Cameras(s.views, w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"])
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_transform_and_backward_match_the_oracle(k):
+    import torch
+    s = scene(k)
+    w = s.meta["world"]
+    say(f"[transform] config {k}: {s.n_views} views, {w['v'].shape[0]} world vertices")
+    ref = oracle.transform(w["v"], w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], s.views)
+    g = np.random.default_rng(k).normal(size=ref.shape).astype(np.float32)
+    g_ref = oracle.transform_bwd(w["v"], w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], s.views, g)
+    ctx = mer.Context(s.views)
+    cams = cams_of(s)
+    vw = to_dev(w["v"])
+    out = torch.full((ref.shape[0], 3), -5.0, dtype=torch.float32, device="cuda")
+    ctx.transform(cams, vw, out)
+    gw = torch.zeros_like(vw)
+    ctx.transform_bwd(cams, vw, to_dev(g), gw)
+    torch.cuda.synchronize()
+    out, gw = out.cpu().numpy(), gw.cpu().numpy()
+    # a pixel coordinate is f x / z + cx: where it is near 0 the two terms
+    # cancel, so its binary32 error scales with them (the principal point)
+    pp = np.zeros_like(ref)
+    for i, row in enumerate(s.views):
+        pp[row[0]: row[0] + row[4], 0] = abs(w["cx"][i])
+        pp[row[0]: row[0] + row[4], 1] = abs(w["cy"][i])
+    assert np.all(np.abs(out - ref) <= 1e-5 * np.maximum(np.maximum(1.0, np.abs(ref)), pp))
+    assert rel_l2(gw, g_ref) <= 1e-5
+
+
+def test_world_step_through_autograd_matches_the_oracle():
+    """Transform -> RenderStep -> L2 loss: the world-vertex gradient equals
+    the oracle's screen gradient pulled back through the oracle transform."""
+    import torch
+
+    from paper_2405_02508_amd.autograd import Renderer, Transform, render
+    s = scene(3)
+    w = s.meta["world"]
+    say("[transform] autograd world step, config 3")
+    r = Renderer(s.views, s.tri, append_z=s.append_z, mask_channel=s.mask_channel)
+    cams = cams_of(s)
+    vw = to_dev(w["v"]).requires_grad_(True)
+    attr = to_dev(s.attr)
+    v = Transform.apply(vw, cams, r)
+    img, tid, _ = render(v, attr, r)
+    g_img = scenes.image_grad(s, 3)
+    (img * to_dev(g_img)).sum().backward()
+    # oracle on the same screen vertices (the transform's own parity is the
+    # test above): forward, fused backward to the screen vertices, then the
+    # transform's backward
+    s2 = dataclasses.replace(s, v=v.detach().cpu().numpy())
+    f = oracle.forward(s2)
+    assert np.array_equal(tid.cpu().numpy(), f["tri_id"])
+    gs, _ = oracle.backward(s2, f, g_img)
+    g_ref = oracle.transform_bwd(w["v"], w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], s.views, gs)
+    assert rel_l2(vw.grad.cpu().numpy(), g_ref) <= 1e-5
