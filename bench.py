@@ -58,7 +58,6 @@ class Step:
         self.bary = torch.empty(n, 2, dtype=torch.float32, device=dev) if store_bary else None
         self.img = torch.empty(n, s.C_e, dtype=torch.float32, device=dev)
         self.interp = self.img if s.C_e == s.C_out else torch.empty(n, s.C_out, dtype=torch.float32, device=dev)
-        self.g = torch.empty(n, s.C_e, dtype=torch.float32, device=dev)
         self.g_v = torch.zeros_like(self.v)
         self.g_attr = torch.zeros_like(self.attr)
         self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile, small_px=small_px,
@@ -74,7 +73,6 @@ class Step:
             self.target.copy_(self.img)
         else:
             self.target.copy_(torch.rand(n, s.C_e, generator=torch.Generator(device=dev).manual_seed(7), device=dev))
-        self.neg2t = (-2.0 * self.target).contiguous()  # L = sum (I - T)^2  ->  g = 2 I - 2 T in one pass
 
     def _assemble(self):
         if self.img is not self.interp:
@@ -89,20 +87,18 @@ class Step:
             c.interpolate(self.attr, self.v, self.tri, self.tid, self.interp, bary=self.bary, append_z=s.append_z)
         self._assemble()
 
-    def loss_grad(self):
-        import torch
-        torch.add(self.neg2t, self.img, alpha=2.0, out=self.g)
-
     def backward(self):
+        """Gradient of L = sum (I - T)^2 to vertices and attributes in one sweep
+        (dL/dI is formed inside the backward kernel; the value of L is not
+        needed for the step and is not computed)."""
         self.g_v.zero_()
         self.g_attr.zero_()
         for c in self.ctxs:
-            c.backward(self.v, self.tri, self.tid, self.attr, self.img, self.g, self.g_attr, self.g_v,
-                       append_z=self.s.append_z)
+            c.backward_l2(self.v, self.tri, self.tid, self.attr, self.img, self.target, self.g_attr, self.g_v,
+                          weight=1.0, append_z=self.s.append_z)
 
     def run(self):
         self.forward()
-        self.loss_grad()
         self.backward()
 
 
@@ -122,7 +118,7 @@ def kernel_times(st, iters, stream):
     """Average duration of each library call on its stream, HIP events."""
     import torch
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    names = ("rasterize", "interpolate", "loss", "backward")
+    names = ("rasterize", "interpolate", "backward")
     acc = {k: 0.0 for k in names}
     for _ in range(iters):
         marks = [ev() for _ in range(6)]
@@ -134,17 +130,16 @@ def kernel_times(st, iters, stream):
             c.interpolate(st.attr, st.v, st.tri, st.tid, st.interp, bary=st.bary, append_z=st.s.append_z)
         marks[2].record(stream)
         st._assemble()
-        st.loss_grad()
         st.g_v.zero_()
         st.g_attr.zero_()
         marks[3].record(stream)
         for c in st.ctxs:
-            c.backward(st.v, st.tri, st.tid, st.attr, st.img, st.g, st.g_attr, st.g_v, append_z=st.s.append_z)
+            c.backward_l2(st.v, st.tri, st.tid, st.attr, st.img, st.target, st.g_attr, st.g_v, weight=1.0,
+                          append_z=st.s.append_z)
         marks[4].record(stream)
         torch.cuda.synchronize()
         acc["rasterize"] += marks[0].elapsed_time(marks[1])
         acc["interpolate"] += marks[1].elapsed_time(marks[2])
-        acc["loss"] += marks[2].elapsed_time(marks[3])
         acc["backward"] += marks[3].elapsed_time(marks[4])
     return {k: acc[k] / iters for k in names}
 

@@ -89,6 +89,7 @@ typedef struct mer_plan {
   int64_t n_part;
   int64_t total_btiles, off_bviewtab; /* 16x16 tiles of the backward sweep */
   int64_t total_v, off_vbase;         /* screen vertices over all views, their per-view prefix */
+  int64_t off_bloss;                  /* per-wave partial sums of the fused L2 loss */
 } mer_plan;
 
 /* One pinhole camera per view for the vertex transform: the rows of R are
@@ -217,6 +218,19 @@ int mer_backward_fused(const mer_plan *plan, const mer_view *views_dev, const fl
                        const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
                        const float *g_img, int C_e, int flags, float *g_attr, float *g_v, void *ws,
                        void *stream);
+
+/* mer_backward_fused for the L2 image loss L = w sum_p sum_c (img - target)^2
+ * (supplement, "Implementation detail": an l2 photometric loss on the
+ * rendered images): dL/d(img) = 2 w (img - target) is formed inside the
+ * sweep instead of being read from memory, and when `loss` (one device
+ * float, accumulated) is not NULL, L over every pixel of every view is added
+ * to it (partial sums per wave of pixels, then one atomic).  target: float
+ * [total_px, C_e], the same layout as img.  Other arguments as
+ * mer_backward_fused. */
+int mer_backward_l2(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                    const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
+                    const float *target, float weight, int C_e, int flags, float *g_attr, float *g_v, float *loss,
+                    void *ws, void *stream);
 
 /* Wait for `stream`, then read the workspace status of the last
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool

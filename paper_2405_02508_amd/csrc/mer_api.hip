@@ -1,6 +1,7 @@
 // mer_api.hip -- the C ABI (include/mer.h): plan, argument checks, launches,
 // status.  No call allocates device memory or synchronises (mer_status aside).
 #include <limits.h>
+#include <cmath>
 #include <string.h>
 
 #include "mer_internal.h"
@@ -87,6 +88,8 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   off = align256(off + 2 * (int64_t)(n_views + 1) * 8);
   P->off_vbase = off;
   off = align256(off + (int64_t)(n_views + 1) * 8);
+  P->off_bloss = off;
+  off = align256(off + btiles * 4 * 4);  // one float per wave
   P->ws_bytes = off;
   return MER_OK;
 }
@@ -138,7 +141,7 @@ int mer_edge_grad(const mer_plan* P, const mer_view* views_dev, const float* v, 
   if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !img || !g_img || !g_v || C_e < 1 || C_e > 64)
     return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
-  return mer::launch_backward(P, views_dev, v, tri, tri_id, nullptr, 0, 0, img, g_img, C_e, C_e,
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, nullptr, 0, 0, img, g_img, nullptr, 0.f, nullptr, C_e, C_e,
                               (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, ws, (hipStream_t)stream);
 }
 
@@ -150,7 +153,8 @@ int mer_interpolate_bwd(const mer_plan* P, const mer_view* views_dev, const floa
     return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
   if (!g_attr && !g_v) return MER_OK;
-  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, nullptr, g_out, ld_out,
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, nullptr, g_out, nullptr,
+                              0.f, nullptr, ld_out,
                               ld_out, MER_SKIP_EDGE, g_attr, g_v, ws, (hipStream_t)stream);
 }
 
@@ -162,9 +166,25 @@ int mer_backward_fused(const mer_plan* P, const mer_view* views_dev, const float
   if (!(flags & MER_SKIP_EDGE) && (!img || !g_v)) return MER_EINVAL;
   if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
-  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, g_img, C_e, C_e,
-                              flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr, g_v, ws,
-                              (hipStream_t)stream);
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, g_img, nullptr, 0.f,
+                              nullptr, C_e, C_e, flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr,
+                              g_v, ws, (hipStream_t)stream);
+}
+
+int mer_backward_l2(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                    const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
+                    const float* target, float weight, int C_e, int flags, float* g_attr, float* g_v, float* loss,
+                    void* ws, void* stream) {
+  const int C = C_a + (append_z ? 1 : 0);
+  if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !img || !target || C_e < 1 || C_e > 64)
+    return MER_EINVAL;
+  if (!std::isfinite(weight)) return MER_EINVAL;
+  if (!(flags & MER_SKIP_EDGE) && !g_v) return MER_EINVAL;
+  if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, nullptr, target, weight,
+                              loss, C_e, C_e, flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr,
+                              g_v, ws, (hipStream_t)stream);
 }
 
 int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) {

@@ -192,13 +192,19 @@ __device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, in
   return -1;
 }
 
+// L2: dL/d(img) = 2 w (img - target) is formed here instead of read from g.
+// LOSS: w * sum (img - target)^2 over each wave's 64 pixels goes to
+// loss_part[4 tile + wave] (computed last, when few registers are live).
+template <bool L2, bool LOSS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_backward(const mer_view* __restrict__ views, int n_views,
                                                   const long long* __restrict__ btile_base,
                                                   const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                   const int32_t* __restrict__ tri_id, const float* __restrict__ attr,
                                                   int C_a, int append_z, const float* __restrict__ img,
                                                   const float* __restrict__ g, int C_e, int ld_g, int flags,
-                                                  float* __restrict__ g_attr, float* __restrict__ g_v) {
+                                                  float* __restrict__ g_attr, float* __restrict__ g_v,
+                                                  const float* __restrict__ target, float w_l2,
+                                                  float* __restrict__ loss_part) {
   __shared__ int s_key[kSlots];
   __shared__ float s_val[kSlots * kNV];
   __shared__ int s_list[kSlots];
@@ -258,10 +264,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     const int axis = dir < 2 ? 0 : 1;
     const long long pA = selfA ? p : pn, pB = selfA ? pn : p;
     float acc = 0.f;
-    for (int c = 0; c < C_e; ++c) {
-      const float gs = g[pA * ld_g + c] + g[pB * ld_g + c];
-      const float di = img[pA * C_e + c] - img[pB * C_e + c];
-      acc += gs * di;
+    const float* ia = img + pA * C_e;
+    const float* ib = img + pB * C_e;
+    if constexpr (L2) {
+      const float* ta = target + pA * C_e;
+      const float* tb = target + pB * C_e;
+      for (int c = 0; c < C_e; ++c) {
+        const float gs = (2.0f * w_l2) * (ia[c] - ta[c]) + (2.0f * w_l2) * (ib[c] - tb[c]);
+        acc += gs * (ia[c] - ib[c]);
+      }
+    } else {
+      const float* ga = g + pA * ld_g;
+      const float* gb = g + pB * ld_g;
+      for (int c = 0; c < C_e; ++c) acc += (ga[c] + gb[c]) * (ia[c] - ib[c]);
     }
     const float dLdp = 0.5f * acc;
     if (tn < 0) {
@@ -335,13 +350,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
 
   // ---- interpolation adjoint and Omega
   if (!(flags & MER_SKIP_INTERP)) {
-    const float* gp = g + (t >= 0 ? p : 0) * ld_g;
+    // this pixel's dL/d(image) row
+    const long long pg = t >= 0 ? p : 0;
+    const float* gp = L2 ? img + pg * C_e : g + pg * ld_g;
+    const float* tp = L2 ? target + pg * C_e : nullptr;
+    auto gown = [&](int c) -> float {
+      if constexpr (L2) return (2.0f * w_l2) * (gp[c] - tp[c]);
+      else return gp[c];
+    };
     long long arow[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) arow[k] = t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0;
     float G[3] = {0.f, 0.f, 0.f};
     for (int c = 0; c < C_a; ++c) {  // uniform trip count: every lane joins the reductions
-      const float gc = t >= 0 ? gp[c] : 0.f;
+      const float gc = t >= 0 ? gown(c) : 0.f;
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         if (t >= 0) G[k] += gc * attr[arow[k] + c];
@@ -358,8 +380,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       if (append_z) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          G[k] += gp[C_a] * S.z[k];
-          gz[k] += pb.b[k] * gp[C_a];
+          G[k] += gown(C_a) * S.z[k];
+          gz[k] += pb.b[k] * gown(C_a);
         }
       }
       const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
@@ -419,6 +441,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       }
     }
   }
+  if constexpr (LOSS) {
+    {
+      float e2 = 0.f;
+      if (inside)
+        for (int c = 0; c < C_e; ++c) {
+          const float d = img[p * C_e + c] - target[p * C_e + c];
+          e2 += d * d;
+        }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
+      if (lane == 0) loss_part[4 * (long long)blockIdx.x + (threadIdx.x >> 6)] = w_l2 * e2;
+    }
+  }
 }
 
 int launch_interpolate(const mer_plan* P, const mer_view* views, const float* attr, int C_a, const float* v,
@@ -433,17 +468,41 @@ int launch_interpolate(const mer_plan* P, const mer_view* views, const float* at
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 
+// Sum of the per-tile loss partials, one workgroup, then one atomic.
+__global__ void __launch_bounds__(1024) k_loss_sum(const float* __restrict__ part, long long n,
+                                                   float* __restrict__ loss) {
+  __shared__ float s_w[16];
+  float a = 0.f;
+  for (long long i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += s_w[i];
+    atomicAdd(loss, t);
+  }
+}
+
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
-                    const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, void* ws,
-                    hipStream_t st) {
+                    const float* g, const float* target, float w_l2, float* loss, int C_e, int ld_g, int flags,
+                    float* g_attr, float* g_v, void* ws, hipStream_t st) {
   long long* tab = (long long*)((char*)ws + P->off_bviewtab);
+  float* bloss = loss ? (float*)((char*)ws + P->off_bloss) : nullptr;
   // 16x16 tile prefix per view; the rasterizer's status words are left alone
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, 4, 4, tab, tab + (P->n_views + 1),
                      (long long*)nullptr);
-  hipLaunchKernelGGL(k_backward, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
-                     tab + (P->n_views + 1), v, tri, tri_id, attr, C_a, append_z, img, g, C_e, ld_g, flags, g_attr,
-                     g_v);
+#define MER_BACKWARD(L2, LOSS)                                                                                 \
+  hipLaunchKernelGGL((k_backward<L2, LOSS>), dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views, \
+                     tab + (P->n_views + 1), v, tri, tri_id, attr, C_a, append_z, img, g, C_e, ld_g, flags, g_attr,  \
+                     g_v, target, w_l2, bloss)
+  if (!target) MER_BACKWARD(false, false);
+  else if (!bloss) MER_BACKWARD(true, false);
+  else MER_BACKWARD(true, true);
+#undef MER_BACKWARD
+  if (bloss) hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(1024), 0, st, bloss, 4 * P->total_btiles, loss);
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 

@@ -16,10 +16,12 @@ int launch_transform_bwd(const mer_plan* P, const mer_view* views, const mer_cam
                          const float* g_screen, float* g_world, void* ws, hipStream_t st);
 int launch_backface(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, float* out, hipStream_t st);
+// g: dL/d(img) rows of ld_g floats, or NULL with target != NULL for the fused
+// L2 loss (dL/d(img) = 2 w (img - target), loss += w sum (img - target)^2)
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
-                    const float* g, int C_e, int ld_g, int flags, float* g_attr, float* g_v, void* ws,
-                    hipStream_t st);
+                    const float* g, const float* target, float w_l2, float* loss, int C_e, int ld_g, int flags,
+                    float* g_attr, float* g_v, void* ws, hipStream_t st);
 // per-view prefix tables (triangles, tiles of 2^tw_log2 x 2^th_log2) and status reset
 __global__ void __launch_bounds__(1024) k_prep(const mer_view* __restrict__ views, int n_views, int tw_log2, int th_log2,
                        long long* __restrict__ tri_base, long long* __restrict__ tile_base,

@@ -20,8 +20,8 @@ SKIP_EDGE = 2
 SKIP_INTERP = 4
 
 SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_interpolate",
-           "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused", "mer_status",
-           "mer_strerror", "mer_version")
+           "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused", "mer_backward_l2",
+           "mer_status", "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -44,7 +44,7 @@ class Plan(ctypes.Structure):
                 ("off_count", ctypes.c_int64), ("off_offs", ctypes.c_int64), ("off_part", ctypes.c_int64),
                 ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("off_key", ctypes.c_int64),
                 ("n_part", ctypes.c_int64), ("total_btiles", ctypes.c_int64), ("off_bviewtab", ctypes.c_int64),
-                ("total_v", ctypes.c_int64), ("off_vbase", ctypes.c_int64)]
+                ("total_v", ctypes.c_int64), ("off_vbase", ctypes.c_int64), ("off_bloss", ctypes.c_int64)]
 
 
 class Camera(ctypes.Structure):
@@ -76,6 +76,8 @@ def lib():
         L.mer_edge_grad.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, P, P]
         L.mer_interpolate_bwd.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, i, P, i, P, P, P, P]
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
+        L.mer_backward_l2.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P, P,
+                                      P, P, P]
         L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
         L.mer_strerror.argtypes = [i]
         L.mer_strerror.restype = ctypes.c_char_p
@@ -301,6 +303,34 @@ class Context:
                                         _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
                                         _ptr(g_img), int(img.shape[1]), int(flags), _ptr(g_attr), _ptr(g_v),
                                         _ptr(self.ws), _stream()))
+
+    def backward_l2(self, v, tri, tri_id, attr, img, target, g_attr, g_v, weight=1.0, loss=None, append_z=False,
+                    flags=0):
+        """backward for L = weight * sum (img - target)^2, dL/dimg formed in the
+        kernel; ``loss`` (one float, accumulated) receives L when given."""
+        import torch
+        _need(img, torch.float32, "img")
+        _need(target, torch.float32, "target")
+        _need(attr, torch.float32, "attr")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(img, "img")
+        self._px(target, "target", int(img.shape[1]))
+        if g_attr is not None:
+            _need(g_attr, torch.float32, "g_attr")
+            self._rows(g_attr, self.need_a, "g_attr", int(attr.shape[1]))
+        if g_v is not None:
+            _need(g_v, torch.float32, "g_v")
+            self._rows(g_v, self.need_v, "g_v", 3)
+        if loss is not None:
+            _need(loss, torch.float32, "loss")
+            if loss.numel() < 1:
+                raise MerError("loss needs one float")
+        _check(lib().mer_backward_l2(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri),
+                                     _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
+                                     _ptr(target), float(weight), int(img.shape[1]), int(flags), _ptr(g_attr),
+                                     _ptr(g_v), _ptr(loss), _ptr(self.ws), _stream()))
 
     def status(self):
         out = (ctypes.c_int64 * 4)()

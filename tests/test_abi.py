@@ -25,7 +25,7 @@ def L():
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(mer_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(mer_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_binding_symbols():
@@ -133,5 +133,12 @@ def test_calls_reject_null_arguments_before_any_launch(L):
                                 None) == -1
     assert L.mer_backward_fused(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, 3, 0, fake, fake, None,
                                 None) == -2
+    f = ctypes.c_float
+    assert L.mer_backward_l2(p, fake, fake, fake, fake, fake, 3, 0, fake, None, f(1.0), 3, 0, fake, fake, None,
+                             fake, None) == -1
+    assert L.mer_backward_l2(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, f(float("nan")), 3, 0, fake, fake,
+                             None, fake, None) == -1
+    assert L.mer_backward_l2(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, f(1.0), 3, 0, fake, fake, None,
+                             None, None) == -2
     assert L.mer_status(p, None, None, (ctypes.c_int64 * 4)()) == -2
     assert L.mer_plan_init(None, 1, None, p) == -1

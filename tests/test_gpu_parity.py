@@ -6,6 +6,7 @@ import functools
 import numpy as np
 import pytest
 
+import oracle
 from paper_2405_02508_amd import scenes
 from tests.gpu_util import compare, run_gpu, run_oracle, say
 
@@ -88,3 +89,38 @@ def test_bin_overflow_fallback_is_exact():
     got = run_gpu(s, g, bin_cap=1)
     compare(got, ref)
     assert got["status"][0]["overflow_tiles"] > 0
+
+
+@pytest.mark.parametrize("k", [2, 4, 5])
+def test_parity_fused_l2_loss(k):
+    """mer_backward_l2 forms dL/dimage = 2 w (I - T) inside the sweep: its
+    gradients match the oracle fed that gradient, and its loss value matches
+    w * sum (I - T)^2 over the GPU image."""
+    import torch
+
+    from paper_2405_02508_amd import mer
+    from tests.gpu_util import rel_l2, to_dev
+    s, _, _ = case(k)
+    say(f"[parity] fused L2 loss config {k}")
+    w = 0.7
+    T = np.random.default_rng(40 + k).uniform(0, 1, size=(s.n_px, s.C_e)).astype(np.float32)
+    v, tri, attr = to_dev(s.v), to_dev(s.tri), to_dev(s.attr)
+    ctx = mer.Context(s.views)
+    tid = torch.empty(s.n_px, dtype=torch.int32, device="cuda")
+    ctx.rasterize(v, tri, tid)
+    interp = torch.empty(s.n_px, s.C_out, dtype=torch.float32, device="cuda")
+    ctx.interpolate(attr, v, tri, tid, interp, append_z=s.append_z)
+    img = interp
+    if s.mask_channel:
+        img = torch.cat([interp, (tid >= 0).float()[:, None]], 1).contiguous()
+    g_v, g_attr = torch.zeros_like(v), torch.zeros_like(attr)
+    loss = torch.full((1,), 0.25, dtype=torch.float32, device="cuda")  # accumulated into
+    ctx.backward_l2(v, tri, tid, attr, img, to_dev(T), g_attr, g_v, weight=w, loss=loss, append_z=s.append_z)
+    torch.cuda.synchronize()
+    I = img.cpu().numpy().astype(np.float64)
+    want = 0.25 + w * ((I - T) ** 2).sum()
+    assert abs(float(loss.item()) - want) <= 1e-5 * want
+    f = oracle.forward(s)
+    gv_ref, ga_ref = oracle.backward(s, f, 2.0 * w * (f["image"] - T))
+    assert rel_l2(g_v.cpu().numpy(), gv_ref) <= 1e-5
+    assert rel_l2(g_attr.cpu().numpy(), ga_ref) <= 1e-5
