@@ -2,8 +2,9 @@
 
 A step is one pass of the whole path over one batch of views, with the
 inputs resident in HBM: rasterize (set-up, binning, tiled z-buffer, resolve),
-interpolate, the L2 image loss gradient g = 2 (I - T) (torch), clearing the
-gradient buffers, and the fused micro-edge + interpolation backward.
+interpolate, clearing the gradient buffers, and the fused micro-edge +
+interpolation backward of the L2 image loss L = sum (I - T)^2, whose
+gradient 2 (I - T) is formed inside the backward kernel.
 Batched = all views of the workload in one captured HIP graph; per-view =
 the same calls issued view by view without a graph.
 
