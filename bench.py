@@ -81,11 +81,11 @@ class Step:
             self.img[:, self.s.C_out].copy_((self.tid >= 0).float())
 
     def forward(self):
+        """Rasterize, resolve and interpolate in one pass per plan."""
         s = self.s
         for c in self.ctxs:
-            c.rasterize(self.v, self.tri, self.tid, self.depth, self.bary)
-        for c in self.ctxs:
-            c.interpolate(self.attr, self.v, self.tri, self.tid, self.interp, bary=self.bary, append_z=s.append_z)
+            c.rasterize_interpolate(self.v, self.tri, self.tid, self.attr, self.interp, depth=self.depth,
+                                    bary=self.bary, append_z=s.append_z)
         self._assemble()
 
     def backward(self):
@@ -119,16 +119,15 @@ def kernel_times(st, iters, stream):
     """Average duration of each library call on its stream, HIP events."""
     import torch
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    names = ("rasterize", "interpolate", "backward")
+    names = ("rasterize_interpolate", "backward")
     acc = {k: 0.0 for k in names}
     for _ in range(iters):
         marks = [ev() for _ in range(6)]
         marks[0].record(stream)
         for c in st.ctxs:
-            c.rasterize(st.v, st.tri, st.tid, st.depth, st.bary)
+            c.rasterize_interpolate(st.v, st.tri, st.tid, st.attr, st.interp, depth=st.depth, bary=st.bary,
+                                    append_z=st.s.append_z)
         marks[1].record(stream)
-        for c in st.ctxs:
-            c.interpolate(st.attr, st.v, st.tri, st.tid, st.interp, bary=st.bary, append_z=st.s.append_z)
         marks[2].record(stream)
         st._assemble()
         st.g_v.zero_()
@@ -139,8 +138,7 @@ def kernel_times(st, iters, stream):
                           append_z=st.s.append_z)
         marks[4].record(stream)
         torch.cuda.synchronize()
-        acc["rasterize"] += marks[0].elapsed_time(marks[1])
-        acc["interpolate"] += marks[1].elapsed_time(marks[2])
+        acc["rasterize_interpolate"] += marks[0].elapsed_time(marks[1])
         acc["backward"] += marks[3].elapsed_time(marks[4])
     return {k: acc[k] / iters for k in names}
 

@@ -147,6 +147,15 @@ int mer_transform_bwd(const mer_plan *plan, const mer_view *views_dev, const mer
 int mer_rasterize(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
                   int32_t *tri_id, float *depth, float *bary, void *ws, void *stream);
 
+/* mer_rasterize and mer_interpolate in one pass: the rasterizer's resolve
+ * also writes the interpolated attributes, with the arithmetic of
+ * mer_interpolate on this call's index image and barycentrics, so `out` is
+ * bit-identical to rasterizing then interpolating.  depth and bary may be
+ * NULL; attr, C_a, append_z and out as mer_interpolate. */
+int mer_rasterize_interpolate(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                              int32_t *tri_id, float *depth, float *bary, const float *attr, int C_a, int append_z,
+                              float *out, void *ws, void *stream);
+
 /* Interpolation module (supplement, "Interpolation module"):
  * out[p, c] = sum_k b_k attr[a_off + tri[t][k], c] for c < C_a and, if
  * append_z, out[p, C_a] = sum_k b_k z_k (screen z of the view's vertices);

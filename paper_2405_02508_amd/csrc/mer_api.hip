@@ -102,7 +102,20 @@ int mer_rasterize(const mer_plan* P, const mer_view* views_dev, const float* v, 
                   float* depth, float* bary, void* ws, void* stream) {
   if (!plan_ok(P) || !views_dev || !tri_id || (P->total_tris > 0 && (!v || !tri))) return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
-  return mer::launch_rasterize(P, views_dev, v, tri, tri_id, depth, bary, ws, (hipStream_t)stream);
+  return mer::launch_rasterize(P, views_dev, v, tri, tri_id, depth, bary, nullptr, 0, 0, nullptr, ws,
+                               (hipStream_t)stream);
+}
+
+int mer_rasterize_interpolate(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                              int32_t* tri_id, float* depth, float* bary, const float* attr, int C_a, int append_z,
+                              float* out, void* ws, void* stream) {
+  if (!plan_ok(P) || !views_dev || !tri_id || !attr || !out || !tri || C_a < 1 || C_a + (append_z ? 1 : 0) > 64)
+    return MER_EINVAL;
+  if (P->total_tris > 0 && !v) return MER_EINVAL;
+  if (append_z && !v) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  return mer::launch_rasterize(P, views_dev, v, tri, tri_id, depth, bary, attr, C_a, append_z ? 1 : 0, out, ws,
+                               (hipStream_t)stream);
 }
 
 int mer_interpolate(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,

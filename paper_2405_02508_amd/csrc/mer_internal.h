@@ -5,8 +5,10 @@
 #include "mer_device.h"
 
 namespace mer {
+// attr/out (nullable): interpolate in the resolve, as launch_interpolate would
 int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, int32_t* tri_id,
-                     float* depth, float* bary, void* ws, hipStream_t st);
+                     float* depth, float* bary, const float* attr, int C_a, int append_z, float* out, void* ws,
+                     hipStream_t st);
 int launch_interpolate(const mer_plan* P, const mer_view* views, const float* attr, int C_a, const float* v,
                        const int32_t* tri, const int32_t* tri_id, const float* bary, int append_z, float* out,
                        hipStream_t st);

@@ -366,7 +366,10 @@ struct __align__(16) TileRec {
 };
 static_assert(sizeof(TileRec) == 80, "tile record layout");
 
-template <int TW, int TH, bool BARY>
+// TRACK: keep the winner's depth-key products along the candidate loop (for
+// stored barycentrics); without it the resolve recomputes them from the
+// winner's vertices when it interpolates.  bary (TRACK only) and out may be NULL.
+template <int TW, int TH, bool TRACK>
 __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ views, int n_views,
                                                    const long long* __restrict__ tri_base,
                                                    const long long* __restrict__ tile_base,
@@ -376,7 +379,8 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    long long px_begin, const float* __restrict__ v,
                                                    const int32_t* __restrict__ tri, int32_t* __restrict__ tri_id,
                                                    float* __restrict__ depth, float* __restrict__ bary,
-                                                   long long* __restrict__ status) {
+                                                   long long* __restrict__ status, const float* __restrict__ attr,
+                                                   int C_a, int append_z, float* __restrict__ out) {
   constexpr int NT = TW * TH;
   constexpr bool kEarlyZ = NT == 64;
   __shared__ TileRec s_tr[NT];
@@ -477,7 +481,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           nq = nq + c;
           const float qk = nq / T.d;
           const unsigned long long k = ((unsigned long long)__float_as_uint(qk) << 32) | T.tneg;
-          if (BARY) {
+          if (TRACK) {
             if (k > best) {
               best = k;
               wa = a;
@@ -504,7 +508,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           float nq = a + b;
           nq = nq + c;
           const unsigned long long k = vis_key(nq / d, t);
-          if (BARY) {
+          if (TRACK) {
             if (k > best) {
               best = k;
               wa = a;
@@ -524,23 +528,48 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const int t = key_tri(best);
   tri_id[p] = t;
   if (depth) depth[p] = t >= 0 ? 1.0f / key_q(best) : 0.0f;
-  if (BARY) {
+  if (TRACK || out) {
     float b0 = 0.f, b1 = 0.f;
     if (t >= 0) {
-      // a winner from the small-triangle pass: the same products from its vertices
-      if (!own) resolve_products(snap_triangle(v, vw, tri_row(tri, vw, t)), px, py, wa, wb, wn);
+      // a winner not tracked here (small-triangle pass, or no tracking): the
+      // same products from its vertices
+      if (!TRACK || !own) resolve_products(snap_triangle(v, vw, tri_row(tri, vw, t)), px, py, wa, wb, wn);
       const float r = __builtin_amdgcn_rcpf(wn);
       b0 = wa * r;
       b1 = wb * r;
     }
-    bary[2 * p] = b0;
-    bary[2 * p + 1] = b1;
+    if (TRACK && bary) {
+      bary[2 * p] = b0;
+      bary[2 * p + 1] = b1;
+    }
+    if (out) {
+      // interpolation, with the arithmetic of the interpolation kernel
+      const int C = C_a + append_z;
+      float* o = out + p * C;
+      if (t >= 0) {
+        const float b2 = (1.0f - b0) - b1;
+        const int32_t* row = tri_row(tri, vw, t);
+        const int i0 = row[0], i1 = row[1], i2 = row[2];
+        const float* a0 = attr + (vw.a_off + i0) * C_a;
+        const float* a1 = attr + (vw.a_off + i1) * C_a;
+        const float* a2 = attr + (vw.a_off + i2) * C_a;
+        for (int c = 0; c < C_a; ++c) o[c] = (b0 * a0[c] + b1 * a1[c]) + b2 * a2[c];
+        if (append_z) {
+          const float* vb = v + vw.v_off * 3;
+          const float z0 = vb[(size_t)i0 * 3 + 2], z1 = vb[(size_t)i1 * 3 + 2], z2 = vb[(size_t)i2 * 3 + 2];
+          o[C_a] = (b0 * z0 + b1 * z1) + b2 * z2;
+        }
+      } else {
+        for (int c = 0; c < C; ++c) o[c] = 0.f;
+      }
+    }
   }
 }
 
 // --------------------------------------------------------------- launch
 int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, int32_t* tri_id,
-                     float* depth, float* bary, void* ws, hipStream_t st) {
+                     float* depth, float* bary, const float* attr, int C_a, int append_z, float* out, void* ws,
+                     hipStream_t st) {
   char* w = (char*)ws;
   long long* viewtab = (long long*)(w + P->off_viewtab);
   long long* tri_base = viewtab;
@@ -580,11 +609,11 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
     if (bary)                                                                                            \
       hipLaunchKernelGGL((k_raster<TW, TH, true>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,      \
                          P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
-                         P->px_begin, v, tri, tri_id, depth, bary, status);                              \
+                         P->px_begin, v, tri, tri_id, depth, bary, status, attr, C_a, append_z, out);    \
     else                                                                                                 \
       hipLaunchKernelGGL((k_raster<TW, TH, false>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,     \
                          P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
-                         P->px_begin, v, tri, tri_id, depth, bary, status);                              \
+                         P->px_begin, v, tri, tri_id, depth, bary, status, attr, C_a, append_z, out);    \
   } while (0)
   if (P->tile_w == 8 && P->tile_h == 8) MER_RASTER(8, 8);
   else if (P->tile_w == 16 && P->tile_h == 16) MER_RASTER(16, 16);

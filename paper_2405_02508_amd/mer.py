@@ -19,9 +19,9 @@ NO_INTERSECT = 1
 SKIP_EDGE = 2
 SKIP_INTERP = 4
 
-SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_interpolate",
-           "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused", "mer_backward_l2",
-           "mer_status", "mer_strerror", "mer_version")
+SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_rasterize_interpolate",
+           "mer_interpolate", "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused",
+           "mer_backward_l2", "mer_status", "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -69,6 +69,7 @@ def lib():
         P, i, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
         L.mer_plan_init.argtypes = [ctypes.POINTER(View), i, ctypes.POINTER(Tuning), ctypes.POINTER(Plan)]
         L.mer_rasterize.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, P]
+        L.mer_rasterize_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, P, i, i, P, P, P]
         L.mer_interpolate.argtypes = [ctypes.POINTER(Plan), P, P, i, P, P, P, P, i, P, P]
         L.mer_backface.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P]
         L.mer_transform.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P]
@@ -207,7 +208,27 @@ class Context:
                                      _ptr(v), _ptr(tri), _ptr(tri_id), _ptr(bary), int(bool(append_z)), _ptr(out),
                                      _stream()))
 
-    # backward -------------------------------------------------------------
+    def rasterize_interpolate(self, v, tri, tri_id, attr, out, depth=None, bary=None, append_z=False):
+        """rasterize + interpolate in one pass (out bit-identical to the two calls)."""
+        import torch
+        _need(v, torch.float32, "v")
+        _need(tri, torch.int32, "tri")
+        _need(tri_id, torch.int32, "tri_id")
+        _need(attr, torch.float32, "attr")
+        _need(out, torch.float32, "out")
+        if depth is not None:
+            _need(depth, torch.float32, "depth")
+        if bary is not None:
+            _need(bary, torch.float32, "bary")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(depth, "depth")
+        self._px(bary, "bary", 2)
+        self._px(out, "out", int(attr.shape[1]) + int(bool(append_z)))
+        _check(lib().mer_rasterize_interpolate(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri),
+                                               _ptr(tri_id), _ptr(depth), _ptr(bary), _ptr(attr), int(attr.shape[1]),
+                                               int(bool(append_z)), _ptr(out), _ptr(self.ws), _stream()))
+
     # vertex transform ---------------------------------------------------
     def transform(self, cams, v_world, v_screen):
         """Screen vertices of every view from world vertices (``cams``: Cameras)."""

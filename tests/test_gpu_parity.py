@@ -124,3 +124,36 @@ def test_parity_fused_l2_loss(k):
     gv_ref, ga_ref = oracle.backward(s, f, 2.0 * w * (f["image"] - T))
     assert rel_l2(g_v.cpu().numpy(), gv_ref) <= 1e-5
     assert rel_l2(g_attr.cpu().numpy(), ga_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("store_bary,small_px", [(True, 16), (False, 16), (True, -1)])
+def test_fused_rasterize_interpolate_equals_two_calls(k, store_bary, small_px):
+    """mer_rasterize_interpolate writes the same bits as mer_rasterize followed
+    by mer_interpolate (stored or recomputed barycentrics), and matches the
+    oracle."""
+    import torch
+
+    from paper_2405_02508_amd import mer
+    from tests.gpu_util import to_dev
+    s, _, ref = case(k)
+    say(f"[parity] fused raster+interp config {k} store_bary={store_bary} small_px={small_px}")
+    v, tri, attr = to_dev(s.v), to_dev(s.tri), to_dev(s.attr)
+    ctx = mer.Context(s.views, small_px=small_px)
+    outs = []
+    for fused in (False, True):
+        tid = torch.full((s.n_px,), -7, dtype=torch.int32, device="cuda")
+        depth = torch.full((s.n_px,), -7.0, dtype=torch.float32, device="cuda")
+        bary = torch.full((s.n_px, 2), -7.0, dtype=torch.float32, device="cuda") if store_bary else None
+        interp = torch.full((s.n_px, s.C_out), -7.0, dtype=torch.float32, device="cuda")
+        if fused:
+            ctx.rasterize_interpolate(v, tri, tid, attr, interp, depth=depth, bary=bary, append_z=s.append_z)
+        else:
+            ctx.rasterize(v, tri, tid, depth, bary)
+            ctx.interpolate(attr, v, tri, tid, interp, bary=bary, append_z=s.append_z)
+        torch.cuda.synchronize()
+        outs.append([x.cpu().numpy() for x in (tid, depth, interp) + ((bary,) if store_bary else ())])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+    assert np.array_equal(outs[1][0], ref["tri_id"])
+    np.testing.assert_array_less(np.abs(outs[1][2] - ref["interp"]), 1e-5 * np.maximum(1, np.abs(ref["interp"])) + 1e-30)
