@@ -129,16 +129,18 @@ class RenderStep(torch.autograd.Function):
     @staticmethod
     def forward(ctx, v, attr, r: Renderer, flags: int = 0):
         vd, ad = v.detach().contiguous(), attr.detach().contiguous()
-        tid, depth, bary = r.rasterize(vd)
+        dev = v.device
+        tid = torch.empty(r.n_px, dtype=torch.int32, device=dev)
+        depth = torch.empty(r.n_px, dtype=torch.float32, device=dev)
+        bary = torch.empty(r.n_px, 2, dtype=torch.float32, device=dev) if r.store_bary else None
         C = attr.shape[1] + int(r.append_z)
         C_e = C + int(r.mask_channel)
-        img = torch.empty(r.n_px, C_e, dtype=torch.float32, device=v.device)
-        if C_e == C:
-            r.ctx.interpolate(ad, vd, r.tri, tid, img, bary=bary, append_z=r.append_z)
-        else:
-            tmp = torch.empty(r.n_px, C, dtype=torch.float32, device=v.device)
-            r.ctx.interpolate(ad, vd, r.tri, tid, tmp, bary=bary, append_z=r.append_z)
-            img[:, :C].copy_(tmp)
+        img = torch.empty(r.n_px, C_e, dtype=torch.float32, device=dev)
+        # one pass: rasterize, resolve and interpolate
+        out = img if C_e == C else torch.empty(r.n_px, C, dtype=torch.float32, device=dev)
+        r.ctx.rasterize_interpolate(vd, r.tri, tid, ad, out, depth=depth, bary=bary, append_z=r.append_z)
+        if C_e != C:
+            img[:, :C].copy_(out)
             img[:, C].copy_(tid >= 0)
         ctx.save_for_backward(vd, ad, tid, img)
         ctx.r = r
