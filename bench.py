@@ -43,7 +43,7 @@ def log(*a):
 class Step:
     """Device buffers and the call sequence of one step for a set of views."""
 
-    def __init__(self, scene, groups, tile, store_bary, dev, small_px=0, bin_cap=0):
+    def __init__(self, scene, groups, tile, store_bary, dev, small_px=0, bin_cap=0, big_tiles=0):
         import torch
 
         from paper_2405_02508_amd import mer
@@ -61,7 +61,7 @@ class Step:
         self.interp = self.img if s.C_e == s.C_out else torch.empty(n, s.C_out, dtype=torch.float32, device=dev)
         self.g_v = torch.zeros_like(self.v)
         self.g_attr = torch.zeros_like(self.attr)
-        self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile, small_px=small_px,
+        self.ctxs = [mer.Context(s.views[grp], device=dev, tile=tile, small_px=small_px, big_tiles=big_tiles,
                                  bin_cap=bin_cap if len(groups) == 1 else 0) for grp in groups]
         # L2 target image rendered once from perturbed vertices (outside the timed region)
         self.target = torch.zeros(n, s.C_e, dtype=torch.float32, device=dev)
@@ -255,15 +255,17 @@ def main():
         from paper_2405_02508_amd import autotune
         t0 = time.perf_counter()
         tu = autotune.tune(s.views, torch.from_numpy(s.v).to(dev), torch.from_numpy(s.tri).to(dev), log=log)
-        tuning = {"tile": list(tu["tile"]), "small_px": tu["small_px"], "bin_cap": tu["bin_cap"],
+        tuning = {"tile": list(tu["tile"]), "small_px": tu["small_px"], "big_tiles": tu["big_tiles"], "bin_cap": tu["bin_cap"],
                   "source": "autotuner (cached)" if tu.get("cached") else "autotuner"}
         log(f"[bench] autotune {time.perf_counter() - t0:.1f}s -> {tuning}")
     else:
-        tuning = {"tile": [int(x) for x in args.tile.split("x")], "small_px": 0, "bin_cap": 0, "source": "flag"}
+        tuning = {"tile": [int(x) for x in args.tile.split("x")], "small_px": 0, "big_tiles": 0, "bin_cap": 0,
+                  "source": "flag"}
     tile = tuple(tuning["tile"])
 
     # ---- batched: every view in one plan, captured in a HIP graph
-    st = Step(s, [list(range(s.n_views))], tile, not s.recompute, dev, tuning["small_px"], tuning["bin_cap"])
+    st = Step(s, [list(range(s.n_views))], tile, not s.recompute, dev, tuning["small_px"], tuning["bin_cap"],
+              tuning["big_tiles"])
     for _ in range(args.warmup):
         st.run()
     torch.cuda.synchronize()
@@ -296,7 +298,8 @@ def main():
     used_graph = graph is not None
     if not args.no_per_view and s.n_views > 1:
         graph = None
-        st_pv = Step(s, [[i] for i in range(s.n_views)], tile, not s.recompute, dev, tuning["small_px"])
+        st_pv = Step(s, [[i] for i in range(s.n_views)], tile, not s.recompute, dev, tuning["small_px"],
+                     big_tiles=tuning["big_tiles"])
         for _ in range(max(1, args.warmup)):
             st_pv.run()
         ms_pv = time_region(st_pv.run, max(2, args.steps // 4), stream)

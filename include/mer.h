@@ -75,7 +75,8 @@ typedef struct mer_tuning {
   int32_t tile_w, tile_h; /* supported: 8x8, 16x16, 32x8, 16x8 */
   int64_t bin_cap;
   int32_t small_px;
-  int32_t reserved; /* set to 0 */
+  int32_t big_tiles; /* a triangle whose box spans more tiles is binned by a
+                        whole wave (0: default 16; negative: never) */
 } mer_tuning;
 
 /* Host-side plan: totals over the view table and the workspace layout.
@@ -90,6 +91,10 @@ typedef struct mer_plan {
   int64_t total_btiles, off_bviewtab; /* 16x16 tiles of the backward sweep */
   int64_t total_v, off_vbase;         /* screen vertices over all views, their per-view prefix */
   int64_t off_bloss;                  /* per-wave partial sums of the fused L2 loss */
+  int64_t off_big, off_bign;          /* per-workgroup lists of large triangles, lengths + offsets */
+  int64_t big_tiles;                  /* see mer_tuning */
+  int64_t n_bingroups, off_bigflat;   /* workgroups of the binning passes; the packed list */
+  int64_t off_bigpart;                /* scan partials of the list lengths */
 } mer_plan;
 
 /* One pinhole camera per view for the vertex transform: the rows of R are

@@ -1,4 +1,5 @@
-"""Autotuner for the rasterizer's tile shape, small-triangle limit and bin pool.
+"""Autotuner for the rasterizer's tile shape, small-triangle limit, large-
+triangle limit and bin pool.
 
 None of these change the results (the visibility rule is order-independent
 and the overflow path is exact); they only change speed and workspace size.
@@ -22,11 +23,11 @@ import numpy as np
 from . import mer
 
 CANDIDATES = (
-    # (tile_w, tile_h, small_px)
-    (8, 8, 16), (8, 8, 64), (8, 8, 256),
-    (16, 16, 16), (16, 16, 64), (16, 16, 256),
-    (32, 8, 64), (16, 8, 64),
-    (8, 8, -1), (16, 16, -1),
+    # (tile_w, tile_h, small_px, big_tiles)
+    (8, 8, 16, 16), (8, 8, 16, -1), (8, 8, 64, 16), (8, 8, 256, 16),
+    (16, 16, 16, 16), (16, 16, 64, 16), (16, 16, 256, 16),
+    (32, 8, 64, 16), (16, 8, 64, 16),
+    (8, 8, -1, 16), (8, 8, -1, -1), (16, 16, -1, 16),
 )
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "mer_autotune.json")
 
@@ -36,7 +37,7 @@ def shape_class(views_i64) -> str:
     px = int((V[:, 6] * V[:, 7]).sum())
     tris = int(V[:, 5].sum())
     b = lambda x: int(round(math.log2(max(x, 1))))  # noqa: E731
-    return f"v{V.shape[0]}-px2^{b(px)}-t2^{b(tris)}"
+    return f"v2-v{V.shape[0]}-px2^{b(px)}-t2^{b(tris)}"
 
 
 def _load(path):
@@ -49,7 +50,7 @@ def _load(path):
 
 def tune(views_i64, v, tri, device="cuda", candidates=CANDIDATES, reps=3, cache_path=DEFAULT_CACHE,
          use_cache=True, log=None):
-    """Return dict(tile=(w, h), small_px=int, bin_cap=int, ms=float, table=[...])."""
+    """Return dict(tile=(w, h), small_px=int, big_tiles=int, bin_cap=int, ms=float, table=[...])."""
     import torch
     key = shape_class(views_i64)
     if use_cache and cache_path:
@@ -65,13 +66,13 @@ def tune(views_i64, v, tri, device="cuda", candidates=CANDIDATES, reps=3, cache_
     stream = torch.cuda.current_stream()
     table = []
     best = None
-    for (tw, th, sp) in candidates:
-        ctx = mer.Context(views_i64, device=device, tile=(tw, th), small_px=sp)
+    for (tw, th, sp, bt) in candidates:
+        ctx = mer.Context(views_i64, device=device, tile=(tw, th), small_px=sp, big_tiles=bt)
         ctx.rasterize(v, tri, tid, depth, bary)
         st = ctx.status()
         cap = int(st["entries"] * 1.25) + 4096
         del ctx
-        ctx = mer.Context(views_i64, device=device, tile=(tw, th), small_px=sp, bin_cap=cap)
+        ctx = mer.Context(views_i64, device=device, tile=(tw, th), small_px=sp, big_tiles=bt, bin_cap=cap)
         ctx.rasterize(v, tri, tid, depth, bary)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -81,7 +82,7 @@ def tune(views_i64, v, tri, device="cuda", candidates=CANDIDATES, reps=3, cache_
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        row = dict(tile=(tw, th), small_px=sp, bin_cap=cap, entries=int(st["entries"]), ms=round(ms, 4))
+        row = dict(tile=(tw, th), small_px=sp, big_tiles=bt, bin_cap=cap, entries=int(st["entries"]), ms=round(ms, 4))
         table.append(row)
         if log:
             log(f"[autotune] {row}")
@@ -92,7 +93,7 @@ def tune(views_i64, v, tri, device="cuda", candidates=CANDIDATES, reps=3, cache_
     out = dict(best, table=table, key=key, cached=False)
     if cache_path:
         data = _load(cache_path)
-        data[key] = {k: out[k] for k in ("tile", "small_px", "bin_cap", "entries", "ms")}
+        data[key] = {k: out[k] for k in ("tile", "small_px", "big_tiles", "bin_cap", "entries", "ms")}
         os.makedirs(os.path.dirname(cache_path), exist_ok=True)
         tmp = cache_path + ".tmp"
         with open(tmp, "w") as f:

@@ -64,6 +64,7 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   if (cap > INT_MAX - 1) cap = INT_MAX - 1;  // a saturated bin offset (INT_MAX) always overflows
   P->bin_cap = cap;
   P->small_px = (tun && tun->small_px != 0) ? (tun->small_px < 0 ? 0 : tun->small_px) : 16;
+  P->big_tiles = (tun && tun->big_tiles != 0) ? (tun->big_tiles < 0 ? INT_MAX : tun->big_tiles) : 16;
   P->n_part = (tiles + 1023) / 1024;
   int64_t off = 0;
   P->off_viewtab = off;
@@ -90,6 +91,16 @@ int mer_plan_init(const mer_view* views, int n_views, const mer_tuning* tun, mer
   off = align256(off + (int64_t)(n_views + 1) * 8);
   P->off_bloss = off;
   off = align256(off + btiles * 4 * 4);  // one float per wave
+  const int64_t bin_groups = (tris + mer::kBinBlock - 1) / mer::kBinBlock;
+  P->off_big = off;
+  off = align256(off + bin_groups * mer::kBinBlock * 4);
+  P->n_bingroups = bin_groups;
+  P->off_bign = off;
+  off = align256(off + (bin_groups * 2 + 1) * 4);  // list lengths, then their offsets
+  P->off_bigpart = off;
+  off = align256(off + (bin_groups + 1023) / 1024 * 8);
+  P->off_bigflat = off;
+  off = align256(off + tris * 4);
   P->ws_bytes = off;
   return MER_OK;
 }

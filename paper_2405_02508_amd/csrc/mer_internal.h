@@ -5,6 +5,8 @@
 #include "mer_device.h"
 
 namespace mer {
+constexpr int kBinBlock = 256;  // threads per workgroup of the binning passes (one triangle each)
+
 // attr/out (nullable): interpolate in the resolve, as launch_interpolate would
 int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, int32_t* tri_id,
                      float* depth, float* bary, const float* attr, int C_a, int append_z, float* out, void* ws,

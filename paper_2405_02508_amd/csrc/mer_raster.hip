@@ -77,25 +77,50 @@ struct BBox {
   short x0, y0, x1, y1;  // inclusive pixel range; x0 > x1 when empty/culled
 };
 
-// Every tile (global index) whose box of pixel centres inside bb the record
-// may cover (box_may_cover); the count and fill passes use the same test.
+// Triangles whose box spans more than big_tiles tiles (a plan setting) are
+// listed by the count pass and binned by k_bin_big, where a whole wave walks
+// one triangle's tiles 64 at a time: a few large triangles then do not hold
+// every lane of their wave in a long loop.
+
+__device__ __forceinline__ int box_tiles(const BBox& bb, int tw_log2, int th_log2) {
+  return ((bb.x1 >> tw_log2) - (bb.x0 >> tw_log2) + 1) * ((bb.y1 >> th_log2) - (bb.y0 >> th_log2) + 1);
+}
+
+// The box's tile k (row-major) and the part of the box inside it; f(global
+// tile) when box_may_cover accepts it -- the one test of every binning pass.
 template <typename F>
-__device__ __forceinline__ void for_each_tile(const Rec& R, const BBox& bb, const mer_view& vw, long long base,
-                                              int tw_log2, int th_log2, F f) {
-  const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
+__device__ __forceinline__ void box_tile_test(const Rec& R, const BBox& bb, int tiles_x, long long base, int tw_log2,
+                                              int th_log2, int tx, int ty, F f) {
+  const int bx0 = max(tx << tw_log2, (int)bb.x0), bx1 = min(((tx + 1) << tw_log2) - 1, (int)bb.x1);
+  const int by0 = max(ty << th_log2, (int)bb.y0), by1 = min(((ty + 1) << th_log2) - 1, (int)bb.y1);
+  if (box_may_cover(R, bx0, by0, bx1, by1)) f((int)(base + (long long)ty * tiles_x + tx));
+}
+
+template <typename F>
+__device__ __forceinline__ void for_each_tile(const Rec& R, const BBox& bb, int W, long long base, int tw_log2,
+                                              int th_log2, F f) {
+  const int tiles_x = (W + (1 << tw_log2) - 1) >> tw_log2;
   for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
-    for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx) {
-      const int bx0 = max(tx << tw_log2, (int)bb.x0), bx1 = min(((tx + 1) << tw_log2) - 1, (int)bb.x1);
-      const int by0 = max(ty << th_log2, (int)bb.y0), by1 = min(((ty + 1) << th_log2) - 1, (int)bb.y1);
-      if (box_may_cover(R, bx0, by0, bx1, by1)) f((int)(base + (long long)ty * tiles_x + tx));
-    }
+    for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx)
+      box_tile_test(R, bb, tiles_x, base, tw_log2, th_log2, tx, ty, f);
+}
+
+// A whole wave over one (wave-uniform) triangle's tiles, lane k taking tiles
+// k, k + 64, ...
+template <typename F>
+__device__ __forceinline__ void wave_each_tile(const Rec& R, const BBox& bb, int W, long long base, int tw_log2,
+                                               int th_log2, F f) {
+  const int tiles_x = (W + (1 << tw_log2) - 1) >> tw_log2;
+  const int tx0 = bb.x0 >> tw_log2, ty0 = bb.y0 >> th_log2, ntx = (bb.x1 >> tw_log2) - tx0 + 1;
+  const int nt = box_tiles(bb, tw_log2, th_log2);
+  for (int k = threadIdx.x & 63; k < nt; k += 64)
+    box_tile_test(R, bb, tiles_x, base, tw_log2, th_log2, tx0 + k % ntx, ty0 + k / ntx, f);
 }
 
 // Workgroup table of tile counters: the count and fill passes add into LDS
 // and touch each tile's global counter once per workgroup.  The table stops
 // taking new tiles at 3/4 occupancy (a workgroup of large triangles can meet
 // thousands of tiles); tiles left out use their global counter directly.
-constexpr int kBinBlock = 256;  // threads per workgroup of the count and fill passes
 constexpr int kBinLog2 = 10;    // table of 2^kBinLog2 tile slots
 constexpr int kBinSlots = 1 << kBinLog2;
 constexpr int kBinFull = kBinSlots * 3 / 4;
@@ -136,12 +161,16 @@ __global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict_
                                                const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                const long long* __restrict__ tri_base,
                                                const long long* __restrict__ tile_base, long long total_tris,
-                                               int tw_log2, int th_log2, int small_px, long long px_begin,
+                                               int tw_log2, int th_log2, int small_px, int big_tiles,
+                                               long long px_begin,
                                                Rec* __restrict__ rec, BBox* __restrict__ bbox,
                                                int* __restrict__ count, unsigned long long* __restrict__ key,
-                                               long long* __restrict__ status) {
+                                               long long* __restrict__ status, int* __restrict__ big,
+                                               int* __restrict__ big_n) {
   __shared__ int s_tkey[kBinSlots], s_tcnt[kBinSlots], s_nocc;
+  __shared__ int s_big[kBinBlock], s_nbig;
   clear_tile_table(s_tkey, s_tcnt, &s_nocc);
+  if (threadIdx.x == 0) s_nbig = 0;
   __syncthreads();
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   bool culled = false;
@@ -188,19 +217,27 @@ __global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict_
         bb.x1 = (short)pxb;
         bb.y0 = (short)pya;
         bb.y1 = (short)pyb;
-        for_each_tile(R, bb, vw, tile_base[vi], tw_log2, th_log2, [&](int gt) {
-          const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
-          if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
-          else atomicAdd(count + gt, 1);
-        });
+        if (box_tiles(bb, tw_log2, th_log2) > big_tiles) {
+          s_big[atomicAdd(&s_nbig, 1)] = (int)g;  // counted by k_bin_big
+        } else {
+          for_each_tile(R, bb, vw.W, tile_base[vi], tw_log2, th_log2, [&](int gt) {
+            const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
+            if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
+            else atomicAdd(count + gt, 1);
+          });
+        }
       }
     }
     bbox[g] = bb;
   }
   __syncthreads();
-  // one global atomic per (workgroup, tile)
+  // one global atomic per (workgroup, tile); this workgroup's list of large
+  // triangles goes to its own slot of the list
   for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x)
     if (s_tkey[i] >= 0) atomicAdd(count + s_tkey[i], s_tcnt[i]);
+  const int nbig = s_nbig;
+  for (int i = threadIdx.x; i < nbig; i += blockDim.x) big[(long long)blockIdx.x * kBinBlock + i] = s_big[i];
+  if (threadIdx.x == 0) big_n[blockIdx.x] = nbig;
   // one atomic per wave for the culled count
   unsigned long long m = __ballot(culled);
   if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd((unsigned long long*)status + 1, (unsigned long long)__popcll(m));
@@ -268,7 +305,7 @@ __global__ void __launch_bounds__(256) k_scan_parts(long long* __restrict__ part
 
 __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ count, long long n,
                                                     const long long* __restrict__ part, int* __restrict__ offs,
-                                                    long long* __restrict__ status) {
+                                                    long long* __restrict__ total_out) {
   __shared__ long long s_wave[4];
   const long long base = (long long)blockIdx.x * 1024 + threadIdx.x * 4;
   int c[4];
@@ -286,7 +323,7 @@ __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ coun
     ex += c[j];
     if (base + j == n - 1) {
       offs[n] = sat_int(ex);
-      status[2] = ex;
+      *total_out = ex;
     }
   }
 }
@@ -299,7 +336,7 @@ __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ coun
 __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__ views, int n_views,
                                               const long long* __restrict__ tri_base,
                                               const long long* __restrict__ tile_base, long long total_tris,
-                                              int tw_log2, int th_log2, const Rec* __restrict__ rec,
+                                              int tw_log2, int th_log2, int big_tiles, const Rec* __restrict__ rec,
                                               const BBox* __restrict__ bbox,
                                               int* __restrict__ count, const int* __restrict__ offs,
                                               long long bin_cap, int* __restrict__ bins) {
@@ -309,16 +346,16 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   BBox bb = {1, 1, 0, 0};
   if (g < total_tris) bb = bbox[g];
-  const bool live = bb.x0 <= bb.x1;
+  const bool live = bb.x0 <= bb.x1 && box_tiles(bb, tw_log2, th_log2) <= big_tiles;  // large ones: k_bin_big
   Rec R;
-  mer_view vw;
+  int W = 0;
   long long base = 0;
   if (live) {
     const int vi = wave_bucket(tri_base, n_views, g);
-    vw = views[vi];
+    W = views[vi].W;
     base = tile_base[vi];
     R = rec[g];
-    for_each_tile(R, bb, vw, base, tw_log2, th_log2, [&](int gt) {
+    for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
       const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
       if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
     });
@@ -333,14 +370,56 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
     }
   }
   __syncthreads();
+  // the table is frozen: a tile in it takes the next position of the
+  // workgroup's range, any other tile its own global counter
   if (live) {
-    // the table is frozen: a tile in it takes the next position of the
-    // workgroup's range, any other tile its own global counter
-    for_each_tile(R, bb, vw, base, tw_log2, th_log2, [&](int gt) {
+    for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
       const int sl = tile_slot<false>(s_tkey, &s_nocc, gt);
       const long long pos = sl >= 0 ? (long long)s_toff[sl] + atomicAdd(&s_tcnt[sl], 1)
                                     : (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
       if (pos < bin_cap) bins[pos] = (int)g;
+    });
+  }
+}
+
+// ----------------------------------------------------- large triangles
+// The count pass leaves one list of large triangles per workgroup.  The scan
+// kernels turn the list lengths into offsets and a total, k_big_pack copies
+// the lists into one flat list, and k_bin_big walks it: wave v takes
+// triangles v, v + (waves), ... and covers each one's tiles with all 64
+// lanes, straight into the tile counters (one large triangle's tiles are
+// distinct).  FILL = false counts, true writes entries.
+constexpr int kBigGrid = 2048;
+
+__global__ void __launch_bounds__(kBinBlock) k_big_pack(const int* __restrict__ big, const int* __restrict__ big_n,
+                                                        const int* __restrict__ big_off, int* __restrict__ flat) {
+  const int n = big_n[blockIdx.x];
+  if ((int)threadIdx.x < n)
+    flat[big_off[blockIdx.x] + threadIdx.x] = big[(long long)blockIdx.x * kBinBlock + threadIdx.x];
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(256) k_bin_big(const mer_view* __restrict__ views, int n_views,
+                                                 const long long* __restrict__ tri_base,
+                                                 const long long* __restrict__ tile_base, int tw_log2, int th_log2,
+                                                 const Rec* __restrict__ rec, const BBox* __restrict__ bbox,
+                                                 const int* __restrict__ flat, const long long* __restrict__ status,
+                                                 int* __restrict__ count, const int* __restrict__ offs,
+                                                 long long bin_cap, int* __restrict__ bins) {
+  const long long n_big = status[4];
+  const long long waves = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long i = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < n_big; i += waves) {
+    const long long g = __builtin_amdgcn_readfirstlane(flat[i]);
+    const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tri_base, n_views, g));
+    const BBox bb = bbox[g];
+    const Rec R = rec[g];
+    wave_each_tile(R, bb, views[vi].W, tile_base[vi], tw_log2, th_log2, [&](int gt) {
+      if (FILL) {
+        const long long pos = (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
+        if (pos < bin_cap) bins[pos] = (int)g;
+      } else {
+        atomicAdd(count + gt, 1);
+      }
     });
   }
 }
@@ -581,6 +660,11 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   long long* part = (long long*)(w + P->off_part);
   int* bins = (int*)(w + P->off_bins);
   long long* status = (long long*)(w + P->off_status);
+  int* big = (int*)(w + P->off_big);
+  int* big_n = (int*)(w + P->off_bign);
+  int* big_off = big_n + P->n_bingroups;  // n_bingroups + 1 entries
+  long long* big_part = (long long*)(w + P->off_bigpart);
+  int* big_flat = (int*)(w + P->off_bigflat);
   unsigned long long* key = (unsigned long long*)(w + P->off_key);
   const long long npx = P->total_px - P->px_begin;
   const int twl = __builtin_ctz(P->tile_w), thl = __builtin_ctz(P->tile_h);
@@ -593,16 +677,27 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   else
     key = nullptr;  // no small-triangle pass: every pixel starts from background
   if (P->total_tris > 0) {
-    hipLaunchKernelGGL(k_setup, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
-                       v, tri, tri_base, tile_base, P->total_tris, twl, thl, P->small_px, P->px_begin, rec, bbox, count,
-                       key, status);
+    const dim3 bgrid((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), bblock(kBinBlock);
+    hipLaunchKernelGGL(k_setup, bgrid, bblock, 0, st, views, P->n_views, v, tri, tri_base, tile_base, P->total_tris,
+                       twl, thl, P->small_px, (int)P->big_tiles, P->px_begin, rec, bbox, count, key, status, big,
+                       big_n);
+    const long long nl = bgrid.x, nlp = (nl + 1023) / 1024;  // list lengths -> offsets, total in status[4]
+    hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)nlp), dim3(256), 0, st, big_n, nl, big_part);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(256), 0, st, big_part, nlp);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nlp), dim3(256), 0, st, big_n, nl, big_part, big_off, status + 4);
+    hipLaunchKernelGGL(k_big_pack, bgrid, bblock, 0, st, big, big_n, big_off, big_flat);
+    hipLaunchKernelGGL(k_bin_big<false>, dim3(kBigGrid), dim3(256), 0, st, views, P->n_views, tri_base, tile_base, twl,
+                       thl, rec, bbox, big_flat, status, count, offs, P->bin_cap, bins);
   }
   hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part);
   hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(256), 0, st, part, P->n_part);
-  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part, offs, status);
+  hipLaunchKernelGGL(k_scan_final, dim3((unsigned)P->n_part), dim3(256), 0, st, count, nt, part, offs, status + 2);
   if (P->total_tris > 0) {
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), dim3(kBinBlock), 0, st, views, P->n_views,
-                       tri_base, tile_base, P->total_tris, twl, thl, rec, bbox, count, offs, P->bin_cap, bins);
+    const dim3 bgrid((unsigned)((P->total_tris + kBinBlock - 1) / kBinBlock)), bblock(kBinBlock);
+    hipLaunchKernelGGL(k_fill, bgrid, bblock, 0, st, views, P->n_views, tri_base, tile_base, P->total_tris, twl, thl,
+                       (int)P->big_tiles, rec, bbox, count, offs, P->bin_cap, bins);
+    hipLaunchKernelGGL(k_bin_big<true>, dim3(kBigGrid), dim3(256), 0, st, views, P->n_views, tri_base, tile_base, twl,
+                       thl, rec, bbox, big_flat, status, count, offs, P->bin_cap, bins);
   }
 #define MER_RASTER(TW, TH)                                                                               \
   do {                                                                                                   \

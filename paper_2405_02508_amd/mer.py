@@ -32,7 +32,7 @@ class View(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("bin_cap", ctypes.c_int64),
-                ("small_px", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("small_px", ctypes.c_int32), ("big_tiles", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -44,7 +44,10 @@ class Plan(ctypes.Structure):
                 ("off_count", ctypes.c_int64), ("off_offs", ctypes.c_int64), ("off_part", ctypes.c_int64),
                 ("off_bins", ctypes.c_int64), ("off_status", ctypes.c_int64), ("off_key", ctypes.c_int64),
                 ("n_part", ctypes.c_int64), ("total_btiles", ctypes.c_int64), ("off_bviewtab", ctypes.c_int64),
-                ("total_v", ctypes.c_int64), ("off_vbase", ctypes.c_int64), ("off_bloss", ctypes.c_int64)]
+                ("total_v", ctypes.c_int64), ("off_vbase", ctypes.c_int64), ("off_bloss", ctypes.c_int64),
+                ("off_big", ctypes.c_int64), ("off_bign", ctypes.c_int64),
+                ("big_tiles", ctypes.c_int64), ("n_bingroups", ctypes.c_int64), ("off_bigflat", ctypes.c_int64),
+                ("off_bigpart", ctypes.c_int64)]
 
 
 class Camera(ctypes.Structure):
@@ -104,9 +107,9 @@ def views_struct(views_i64: np.ndarray):
     return arr
 
 
-def plan_init(views_i64, tile=(8, 8), bin_cap=0, small_px=0) -> Plan:
+def plan_init(views_i64, tile=(8, 8), bin_cap=0, small_px=0, big_tiles=0) -> Plan:
     vs = views_struct(views_i64)
-    tun = Tuning(int(tile[0]), int(tile[1]), int(bin_cap), int(small_px), 0)
+    tun = Tuning(int(tile[0]), int(tile[1]), int(bin_cap), int(small_px), int(big_tiles))
     P = Plan()
     _check(lib().mer_plan_init(vs, len(vs), ctypes.byref(tun), ctypes.byref(P)))
     return P
@@ -138,10 +141,10 @@ class Context:
     current torch stream.
     """
 
-    def __init__(self, views_i64, device="cuda", tile=(8, 8), bin_cap=0, small_px=0):
+    def __init__(self, views_i64, device="cuda", tile=(8, 8), bin_cap=0, small_px=0, big_tiles=0):
         import torch
         self.views_i64 = np.asarray(views_i64, np.int64)
-        self.plan = plan_init(self.views_i64, tile, bin_cap, small_px)
+        self.plan = plan_init(self.views_i64, tile, bin_cap, small_px, big_tiles)
         raw = bytes(views_struct(self.views_i64))
         self.views_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
         self.ws = torch.empty(int(self.plan.ws_bytes), dtype=torch.uint8, device=device)

@@ -21,7 +21,7 @@ def to_dev(x, dev="cuda"):
 
 
 def run_gpu(s: scenes.Scene, g_np, tile=(8, 8), per_view=False, store_bary=True, flags=0, bin_cap=0,
-            fused=True, small_px=0):
+            fused=True, small_px=0, big_tiles=0):
     """Forward + backward on the GPU; returns numpy outputs."""
     import torch
     dev = torch.device("cuda")
@@ -37,17 +37,20 @@ def run_gpu(s: scenes.Scene, g_np, tile=(8, 8), per_view=False, store_bary=True,
     status = []
     groups = [[i] for i in range(s.n_views)] if per_view else [list(range(s.n_views))]
     for grp in groups:
-        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px)
+        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px,
+                          big_tiles=big_tiles)
         ctx.rasterize(v, tri, tid, depth, bary if store_bary else None)
         status.append(ctx.status())
     for grp in groups:
-        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px)
+        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px,
+                          big_tiles=big_tiles)
         ctx.interpolate(attr, v, tri, tid, interp, bary=bary if store_bary else None, append_z=s.append_z)
     img = interp
     if s.mask_channel:
         img = torch.cat([interp, (tid >= 0).float()[:, None]], 1).contiguous()
     for grp in groups:
-        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px)
+        ctx = mer.Context(s.views[grp], device=dev, tile=tile, bin_cap=bin_cap, small_px=small_px,
+                          big_tiles=big_tiles)
         if fused:
             ctx.backward(v, tri, tid, attr, img, g, g_attr, g_v, append_z=s.append_z, flags=flags)
         else:

@@ -39,7 +39,8 @@ def run_batched(s, g, tune):
 
     from paper_2405_02508_amd import mer
     dev = torch.device("cuda")
-    ctx = mer.Context(s.views, device=dev, tile=tune["tile"], small_px=tune["small_px"], bin_cap=tune["bin_cap"])
+    ctx = mer.Context(s.views, device=dev, tile=tune["tile"], small_px=tune["small_px"], bin_cap=tune["bin_cap"],
+                      big_tiles=tune.get("big_tiles", 0))
     v, tri, attr = to_dev(s.v), to_dev(s.tri), to_dev(s.attr)
     n = s.n_px
     tid = torch.empty(n, dtype=torch.int32, device=dev)

@@ -41,6 +41,19 @@ def test_parity_small_triangle_limit(k, small_px):
     compare(run_gpu(s, g, small_px=small_px), ref)
 
 
+@pytest.mark.parametrize("k", [1, 2, 4, 5])
+@pytest.mark.parametrize("big_tiles,small_px", [(1, -1), (1, 16), (-1, -1), (4, 0)])
+def test_parity_large_triangle_limit(k, big_tiles, small_px):
+    """Triangles walked by a whole wave (nearly all with a limit of 1 tile,
+    none with -1): same index image, same gradients; with a bin pool too small
+    for some tiles as well."""
+    s, g, ref = case(k)
+    say(f"[parity] config {k} big_tiles {big_tiles} small_px {small_px}")
+    compare(run_gpu(s, g, small_px=small_px, big_tiles=big_tiles), ref)
+    if big_tiles == 1:
+        compare(run_gpu(s, g, small_px=small_px, big_tiles=big_tiles, bin_cap=64), ref)
+
+
 @pytest.mark.parametrize("k", [3, 4])
 def test_parity_per_view_launches(k):
     s, g, ref = case(k)
