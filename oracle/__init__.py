@@ -7,8 +7,9 @@ a time, in float64 unless a discrete outcome is decided (see the C file).
 
 Functions follow the paper's modules (supplement, "Implementation detail"):
 rasterisation -> index image, barycentrics/depth at the index image,
-interpolation and its adjoint (the smooth term Omega), and the EdgeGrad
-backward (Sec. 4.2-4.4).
+interpolation and its adjoint (the smooth term Omega), the EdgeGrad
+backward (Sec. 4.2-4.4), and the forward-mode image tangents of both (Sec. 5,
+"Forward gradients").
 """
 from __future__ import annotations
 
@@ -57,6 +58,8 @@ def lib():
         L.orc_interpolate_bwd.argtypes = [P, i, P, i, P, i, i, P, i, P, P, P]
         L.orc_edge_grad.argtypes = [P, i, P, i, i, P, P, P, i, i, P, P, P]
         L.orc_backface.argtypes = [P, i, P, i, i, i, P, P]
+        L.orc_edge_jvp.argtypes = [P, i, P, i, i, P, P, i, i, P, P, P]
+        L.orc_interpolate_jvp.argtypes = [P, i, P, P, i, P, i, i, P, i, P, P]
         _lib = L
     return _lib
 
@@ -159,6 +162,36 @@ def edge_grad(v, tri, H, W, tri_id, img, g, flags=0, g_v=None, want_frag=False, 
     return (g_v, frag) if want_frag else g_v
 
 
+def edge_jvp(v, tri, H, W, tri_id, img, dv, flags=0, dimg=None, counts=None):
+    """Forward-mode micro-edge term: dimg [H*W, C] += per-pixel image
+    tangent for the screen-vertex tangent dv [n_v, 3]."""
+    v, tri, tri_id, img, dv = _f32(v), _i32(tri), _i32(tri_id), _f64(img), _f64(dv)
+    C = img.shape[1]
+    assert dv.shape == (v.shape[0], 3)
+    if dimg is None:
+        dimg = np.zeros((H * W, C))
+    assert dimg.dtype == np.float64 and dimg.flags.c_contiguous and dimg.shape == img.shape
+    if counts is None:
+        counts = np.zeros(4, np.int64)
+    lib().orc_edge_jvp(_p(v), v.shape[0], _p(tri), H, W, _p(tri_id), _p(img), C, int(flags), _p(dv),
+                       _p(dimg), _p(counts))
+    return dimg
+
+
+def interpolate_jvp(attr, v, tri, H, W, tri_id, dv=None, dattr=None, append_z=False):
+    """Tangent of the interpolated image [H*W, C_a + append_z] at a fixed
+    index image, for vertex tangent dv [n_v, 3] and attribute tangent dattr
+    [n_v, C_a] (either may be None)."""
+    attr, v, tri, tri_id = _f32(attr), _f32(v), _i32(tri), _i32(tri_id)
+    C_a = attr.shape[1]
+    dv = None if dv is None else _f64(dv)
+    dattr = None if dattr is None else _f64(dattr)
+    out = np.empty((H * W, C_a + int(append_z)))
+    lib().orc_interpolate_jvp(_p(attr), C_a, _p(dattr), _p(v), v.shape[0], _p(tri), H, W, _p(tri_id),
+                              int(append_z), _p(dv), _p(out))
+    return out
+
+
 # ------------------------------------------------------- whole scene (views)
 def _view_slices(scene, i):
     vw = scene.view(i)
@@ -220,6 +253,30 @@ def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None):
         g_v[vw["v_off"]: vw["v_off"] + vw["n_v"]] += gv
         g_attr[vw["a_off"]: vw["a_off"] + vw["n_v"]] += ga
     return g_v, g_attr
+
+
+def jvp(scene, fwd, dv, dattr=None, flags=0, edge=True, interp=True, views=None):
+    """Forward-mode image tangent over all views, [n_px, C_e]: the
+    interpolated channels' tangent at the fixed index image (first C_out
+    channels; the mask channel has none) plus the micro-edge term over every
+    channel of the image.  dv [sum V_view, 3] screen-vertex tangent, dattr
+    [sum V_attr, C_a] attribute tangent (optional)."""
+    dv = np.asarray(dv, np.float64)
+    dimg = np.zeros((scene.n_px, scene.C_e))
+    for i in (range(scene.n_views) if views is None else views):
+        vw, vs, ts, ats = _view_slices(scene, i)
+        H, W, o = vw["H"], vw["W"], vw["px_off"]
+        sl = slice(o, o + H * W)
+        tid = fwd["tri_id"][sl]
+        dvs = dv[vw["v_off"]: vw["v_off"] + vw["n_v"]]
+        d = np.zeros((H * W, scene.C_e))
+        if interp:
+            da = None if dattr is None else np.asarray(dattr, np.float64)[vw["a_off"]: vw["a_off"] + vw["n_v"]]
+            d[:, :scene.C_out] = interpolate_jvp(ats, vs, ts, H, W, tid, dvs, da, scene.append_z)
+        if edge:
+            edge_jvp(vs, ts, H, W, tid, fwd["image"][sl], dvs, flags=flags, dimg=d)
+        dimg[sl] = d
+    return dimg
 
 
 def step_view(scene, i, target_value=0.5):

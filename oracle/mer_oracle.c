@@ -29,6 +29,9 @@
  *     of an overhang, and for an intersection dp/dr from the slopes of the
  *     two planes in the (axis, 1/z) slice; then fragment gradients go to the
  *     vertices through the screen-space barycentric weights.
+ *   - forward mode (Sec. 5, "Forward gradients"): the per-pixel image tangent
+ *     for a tangent of the screen vertices (and attributes), the transpose of
+ *     the two reverse-mode parts above.
  *
  * Precision: binary64 throughout, except the two places where a floating
  * point result decides a discrete outcome, which are taken in binary32 in a
@@ -472,4 +475,151 @@ void orc_edge_grad(const float *v, int n_v, const int32_t *tri, int H, int W, co
       }
     }
   free(r);
+}
+
+/* -------------------------------------------------------- forward mode */
+/* Forward-mode (per-pixel) derivatives of the image with respect to a
+ * tangent dv[n_v*3] of the screen vertices (Sec. 5 "Forward gradients": the
+ * derivative of every pixel with respect to one scene parameter).  Each part
+ * is the transpose of its reverse-mode counterpart above, so that for any g
+ * the sum over pixels of g . dimg equals the sum over vertices of
+ * (dL/dv) . dv computed by the backward functions. */
+
+/* Tangent of the fragment seen at pixel (px, py) on triangle T: the point
+ * with the fixed screen barycentrics of that centre, whose (x, y) move by
+ * sum_k beta_k (dx_k, dy_k) and whose 1/z moves by sum_k beta_k d(1/z_k),
+ * with d(1/z_k) = -(1/z_k)^2 dz_k. */
+static void orc_frag_tangent(const orc_tri *T, int px, int py, const double *dv, double dr[3]) {
+  double bt[3];
+  orc_beta(T, px, py, bt);
+  dr[0] = dr[1] = dr[2] = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double *d = dv + 3 * (int64_t)T->idx[k];
+    dr[0] += bt[k] * d[0];
+    dr[1] += bt[k] * d[1];
+    dr[2] += bt[k] * (-(T->q[k] * T->q[k])) * d[2];
+  }
+}
+
+/* dimg[H*W*C] += the micro-edge term: for every pair of 4-neighbours A, B
+ * (B right of or below A) with different triangle ids, classified exactly as
+ * in orc_edge_grad, the edge position p moves by dp (overhang: the axis
+ * component of the foreground fragment's tangent; intersection: the
+ * slope-form combination of both fragments' tangents), and both pixels of the
+ * pair change by 1/2 (IA - IB) dp, channel by channel. */
+void orc_edge_jvp(const float *v, int n_v, const int32_t *tri, int H, int W, const int32_t *tri_id,
+                  const double *img, int C, int flags, const double *dv, double *dimg, int64_t *counts) {
+  orc_tri TA, TB;
+  int64_t E[3];
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px)
+      for (int axis = 0; axis < 2; ++axis) {
+        if ((flags & ORC_PAIRS_H_ONLY) && axis != 0) continue;
+        if ((flags & ORC_PAIRS_V_ONLY) && axis != 1) continue;
+        int qx = px + (axis == 0), qy = py + (axis == 1);
+        if (qx >= W || qy >= H) continue;
+        int64_t A = (int64_t)py * W + px, B = (int64_t)qy * W + qx;
+        int tA = tri_id[A], tB = tri_id[B];
+        if (tA == tB) continue;
+        int fg = -1; /* 0: A, 1: B */
+        int inter = 0;
+        if (tA >= 0) orc_setup(v, n_v, tri, tA, &TA);
+        if (tB >= 0) orc_setup(v, n_v, tri, tB, &TB);
+        if (tA < 0) fg = 1;
+        else if (tB < 0) fg = 0;
+        else {
+          int cA = TB.ok && orc_cover(&TB, px, py, E);
+          int cB = TA.ok && orc_cover(&TA, qx, qy, E);
+          if (!cA && !cB) { if (counts) counts[2]++; continue; }
+          if (cA && !cB) fg = 0;
+          else if (!cA && cB) fg = 1;
+          else inter = 1;
+        }
+        double dp;
+        if (!inter) {
+          if (counts) counts[0]++;
+          const orc_tri *T = fg == 0 ? &TA : &TB;
+          if (!T->ok) continue;
+          double dr[3];
+          orc_frag_tangent(T, fg == 0 ? px : qx, fg == 0 ? py : qy, dv, dr);
+          dp = dr[axis];
+        } else {
+          if (flags & ORC_NO_INTERSECT) continue;
+          float sA = orc_slope32(&TA, axis), sB = orc_slope32(&TB, axis);
+          float dlt = sB - sA;
+          if (!(dlt > 0.0f) || !isfinite(dlt)) { if (counts) counts[3]++; continue; }
+          if (counts) counts[1]++;
+          double drA[3], drB[3];
+          orc_frag_tangent(&TA, px, py, dv, drA);
+          orc_frag_tangent(&TB, qx, qy, dv, drB);
+          dp = ((-(double)sA) * drA[axis] + drA[2] + (double)sB * drB[axis] - drB[2]) / (double)dlt;
+        }
+        for (int c = 0; c < C; ++c) {
+          double h = 0.5 * (img[A * C + c] - img[B * C + c]) * dp;
+          dimg[A * C + c] += h;
+          dimg[B * C + c] += h;
+        }
+      }
+}
+
+/* dout[H*W*(C_a+append_z)] = tangent of orc_interpolate at a fixed index
+ * image when the screen vertices move by dv (nullable) and the attributes by
+ * dattr[n_v*C_a] (nullable): the forward derivative of b_k = w_k / sum_j w_j
+ * with w_k = beta_k / z_k, beta_k = E_k / D (continuous; snapping is taken as
+ * the identity), and of sum_k b_k a_kc.  Background pixels get 0. */
+void orc_interpolate_jvp(const float *attr, int C_a, const double *dattr, const float *v, int n_v,
+                         const int32_t *tri, int H, int W, const int32_t *tri_id, int append_z,
+                         const double *dv, double *dout) {
+  int C = C_a + (append_z ? 1 : 0);
+  orc_tri T;
+  for (int py = 0; py < H; ++py)
+    for (int px = 0; px < W; ++px) {
+      int64_t p = (int64_t)py * W + px;
+      for (int c = 0; c < C; ++c) dout[p * C + c] = 0.0;
+      int t = tri_id[p];
+      if (t < 0) continue;
+      orc_setup(v, n_v, tri, t, &T);
+      if (!T.ok) continue;
+      double bt[3], w[3], b[3], Wsum = 0.0;
+      orc_beta(&T, px, py, bt);
+      for (int k = 0; k < 3; ++k) { w[k] = bt[k] * T.q[k]; Wsum += w[k]; }
+      for (int k = 0; k < 3; ++k) b[k] = w[k] / Wsum;
+      double db[3] = {0, 0, 0}, dz[3] = {0, 0, 0};
+      if (dv) {
+        /* moving every vertex by dv_j moves the material point at this
+         * centre by delta = sum_j beta_j dv_j (xy), so beta_i changes by
+         * -grad_P beta_i . delta */
+        double ex = 0.0, ey = 0.0;
+        for (int j = 0; j < 3; ++j) {
+          ex += bt[j] * dv[3 * (int64_t)T.idx[j] + 0];
+          ey += bt[j] * dv[3 * (int64_t)T.idx[j] + 1];
+          dz[j] = dv[3 * (int64_t)T.idx[j] + 2];
+        }
+        double dw[3], dW = 0.0;
+        for (int i = 0; i < 3; ++i) {
+          int a = (i + 1) % 3, bb = (i + 2) % 3;
+          double gxi = -256.0 * (double)(T.Y[bb] - T.Y[a]) / (double)T.D;
+          double gyi = 256.0 * (double)(T.X[bb] - T.X[a]) / (double)T.D;
+          double dbeta = -(gxi * ex + gyi * ey);
+          double dq = -(T.q[i] * T.q[i]) * dz[i];
+          dw[i] = dbeta * T.q[i] + bt[i] * dq;
+          dW += dw[i];
+        }
+        for (int k = 0; k < 3; ++k) db[k] = (dw[k] - b[k] * dW) / Wsum;
+      }
+      for (int c = 0; c < C_a; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          int64_t vi = T.idx[k];
+          acc += db[k] * (double)attr[vi * C_a + c];
+          if (dattr) acc += b[k] * dattr[vi * C_a + c];
+        }
+        dout[p * C + c] = acc;
+      }
+      if (append_z) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += db[k] * T.z[k] + b[k] * dz[k];
+        dout[p * C + C_a] = acc;
+      }
+    }
 }

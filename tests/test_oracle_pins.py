@@ -706,3 +706,164 @@ def test_p14_backward_matches_central_differences_and_sums_views():
     per_view = sum(oracle.transform_bwd(pts, R[i:i + 1], C[i:i + 1], f[i:i + 1], cx[i:i + 1], cy[i:i + 1], [0],
                                         _views_for(1, n), g[i * n:(i + 1) * n]) for i in range(3))
     np.testing.assert_allclose(got, per_view, rtol=1e-12, atol=1e-12)
+
+
+# -------------------------------------------- P15 forward-mode image tangents
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_p15_jvp_axis_aligned_edge_closed_form(side):
+    """Sec. 5 "Forward gradients": moving a vertical edge of a colour-c
+    region by dx changes only the two pixels that straddle it, each by
+    half the jump times dx, so every row changes by c dx in total (the
+    derivative of the row's covered length times c)."""
+    H, W, X, c = 16, 24, 10.0, float(np.float32(0.7))
+    v, t = (quad(-10, -10, X, H + 10) if side == "left" else quad(X, -10, W + 10, H + 10))
+    attr = np.full((4, 1), c, np.float32)
+    tid = oracle.rasterize(v, t, H, W)
+    img = oracle.interpolate(attr, v, t, H, W, tid)
+    dv = np.zeros((4, 3))
+    dv[:, 0] = 1.0
+    d = oracle.edge_jvp(v, t, H, W, tid, img, dv).reshape(H, W)
+    sgn = 1.0 if side == "left" else -1.0
+    expect = np.zeros((H, W))
+    expect[:, 9] = expect[:, 10] = sgn * 0.5 * c
+    np.testing.assert_array_equal(d, expect)
+    # the colour is constant, so the interior tangent is zero
+    assert np.abs(oracle.interpolate_jvp(attr, v, t, H, W, tid, dv)).max() < 1e-12
+    # a y translation moves no vertical edge
+    dv = np.zeros((4, 3))
+    dv[:, 1] = 1.0
+    assert np.abs(oracle.edge_jvp(v, t, H, W, tid, img, dv)).max() == 0.0
+
+
+def test_p15_jvp_intersection_closed_form():
+    """Eq. grad_int: planes q = s x + c crossing on a vertical line; shifting
+    plane B by dc (in 1/z) moves the crossing by -dc / (sB - sA), and the two
+    pixels that straddle it change by half the colour jump times that."""
+    H, W = 8, 32
+    v, t, attr, (sA, cA, sB, cB, colA, colB) = _crossing_planes(H, W)
+    tid = oracle.rasterize(v, t, H, W)
+    img = oracle.interpolate(attr, v, t, H, W, tid)
+    dc = 1.0
+    dv = np.zeros((8, 3))
+    z = v[4:, 2].astype(np.float64)
+    dv[4:, 2] = -z * z * dc                                  # dq = -q^2 dz = dc
+    d = oracle.edge_jvp(v, t, H, W, tid, img, dv).reshape(H, W)
+    dx = -dc / (sB - sA)
+    expect = 0.5 * (colA - colB) * dx
+    np.testing.assert_allclose(d[:, 15], expect, rtol=2e-5)
+    np.testing.assert_allclose(d[:, 16], expect, rtol=2e-5)
+    d[:, 15:17] = 0
+    assert np.abs(d).max() == 0.0
+    # moving both planes rigidly in x moves the crossing by the same amount
+    dv = np.zeros((8, 3))
+    dv[:, 0] = 1.0
+    d = oracle.edge_jvp(v, t, H, W, tid, img, dv).reshape(H, W)
+    np.testing.assert_allclose(d[:, 15:17], 0.5 * (colA - colB), rtol=1e-5)
+    # ablation flag: intersections contribute nothing
+    assert np.abs(oracle.edge_jvp(v, t, H, W, tid, img, dv, flags=oracle.NO_INTERSECT)).max() == 0.0
+
+
+def test_p15_jvp_closed_shape_translation_sums_to_zero():
+    """A constant-colour closed silhouette inside the image keeps its area
+    under translation: the image tangent sums to zero, with nonzero entries
+    only on the silhouette."""
+    from paper_2405_02508_amd import scenes
+    s = scenes.make_config(1)
+    attr = np.full((s.v.shape[0], 1), 0.6, np.float32)
+    tid = oracle.rasterize(s.v, s.tri, 64, 64)
+    img = oracle.interpolate(attr, s.v, s.tri, 64, 64, tid)
+    for k in (0, 1):
+        dv = np.zeros((s.v.shape[0], 3))
+        dv[:, k] = 1.0
+        d = oracle.edge_jvp(s.v, s.tri, 64, 64, tid, img, dv)
+        assert np.abs(d).max() > 0.1
+        assert abs(d.sum()) < 1e-9
+        grid = (tid >= 0).reshape(64, 64)
+        edge = np.zeros_like(grid)
+        edge[:, :-1] |= grid[:, :-1] != grid[:, 1:]
+        edge[:, 1:] |= grid[:, :-1] != grid[:, 1:]
+        edge[:-1] |= grid[:-1] != grid[1:]
+        edge[1:] |= grid[:-1] != grid[1:]
+        assert np.all(d.reshape(64, 64)[~edge] == 0.0)
+
+
+def _jvp_scenes():
+    S = dict(_tiny_scenes())
+    v, t, attr, _ = _crossing_planes(8, 32)
+    S["planes"] = (v, t, attr)
+    from paper_2405_02508_amd import scenes
+    s = scenes.make_config(1)
+    S["sphere"] = (s.v, s.tri, s.attr)
+    return S
+
+
+@pytest.mark.parametrize("name", ["one", "overlap", "intersect", "planes", "sphere"])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_p15_jvp_is_the_transpose_of_the_backward(name, flags):
+    """For any dL/dimage g and tangents dv, dattr: sum g . J(dv, dattr) equals
+    dL/dv . dv + dL/dattr . dattr from the (separately pinned) reverse-mode
+    oracle, for the edge term and the interpolation term each."""
+    v, t, attr = _jvp_scenes()[name]
+    H, W = (8, 32) if name == "planes" else (64, 64)
+    rng = np.random.default_rng(15 + flags)
+    tid = oracle.rasterize(v, t, H, W)
+    img = oracle.interpolate(attr, v, t, H, W, tid, append_z=True)
+    C = img.shape[1]
+    g = rng.normal(size=(H * W, C))
+    dv = rng.normal(size=(v.shape[0], 3))
+    dv[:, 2] *= 0.1
+    da = rng.normal(size=attr.shape)
+    counts = np.zeros(4, np.int64)
+    d = oracle.edge_jvp(v, t, H, W, tid, img, dv, flags=flags, counts=counts)
+    gv = oracle.edge_grad(v, t, H, W, tid, img, g, flags=flags)
+    lhs, rhs = float((g * d).sum()), float((gv * dv).sum())
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs)), (lhs, rhs)
+    if name != "planes":                  # the planes scene has intersection pairs only
+        assert counts[0] > 0 and abs(lhs) > 1e-3
+    if name in ("intersect", "planes") and flags == 0:
+        assert counts[1] > 0 and abs(lhs) > 1e-3
+    di = oracle.interpolate_jvp(attr, v, t, H, W, tid, dv, da, append_z=True)
+    ga, gvi = oracle.interpolate_bwd(attr, v, t, H, W, tid, g, True)
+    lhs, rhs = float((g * di).sum()), float((gvi * dv).sum() + (ga * da).sum())
+    assert abs(lhs - rhs) <= 1e-10 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+@pytest.mark.parametrize("append_z", [False, True])
+def test_p15_interpolate_jvp_matches_torch_jvp(append_z):
+    """The interior tangent is the forward derivative of the continuous
+    interpolation at a fixed index image: binary64 torch.func.jvp of the
+    formulas written out again."""
+    rng = np.random.default_rng(7)
+    H, W = 20, 24
+    P = np.round(rng.uniform(-4, 28, size=(12, 2)) * 256) / 256
+    v = np.concatenate([P, rng.uniform(1.5, 4.0, size=(12, 1))], 1).astype(np.float32)
+    t = np.arange(12, dtype=np.int32).reshape(4, 3)
+    attr = rng.uniform(0, 1, size=(12, 2)).astype(np.float32)
+    tid = oracle.rasterize(v, t, H, W)
+    assert (tid >= 0).sum() > 60
+    dv = rng.normal(size=(12, 3))
+    da = rng.normal(size=(12, 2))
+    d = oracle.interpolate_jvp(attr, v, t, H, W, tid, dv, da, append_z)
+    ref = truth.interp_jvp_torch(v, t, attr, H, W, tid, dv, da, append_z)
+    np.testing.assert_allclose(d, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+
+
+def test_p15_jvp_vs_finite_differences_of_supersampled_render():
+    """The whole tangent (edge + interior) summed against smooth weights
+    matches central differences of a 256-sample area-coverage render, within
+    the paper's own backward-gradient error bound."""
+    H = W = 64
+    wgt = _weights(H, W, 3)
+    for name in ("one", "overlap", "intersect"):
+        v, t, attr = _tiny_scenes()[name]
+        tid = oracle.rasterize(v, t, H, W)
+        img = oracle.interpolate(attr, v, t, H, W, tid)
+        ana, fd = [], []
+        for dv in _param_dirs(v, ["tx0", "ty0", "v1x", "v2y"]):
+            d = oracle.edge_jvp(v, t, H, W, tid, img, dv) + oracle.interpolate_jvp(attr, v, t, H, W, tid, dv)
+            ana.append(float((d * wgt).sum()))
+            Lp = (truth.render_supersampled(v + 0.5 * dv, t, attr, H, W) * wgt).sum()
+            Lm = (truth.render_supersampled(v - 0.5 * dv, t, attr, H, W) * wgt).sum()
+            fd.append((Lp - Lm) / 1.0)
+        ana, fd = np.array(ana), np.array(fd)
+        assert np.linalg.norm(ana - fd) / np.linalg.norm(fd) <= _tol_from_paper(), (name, ana, fd)

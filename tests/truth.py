@@ -105,3 +105,40 @@ def omega_torch(v, tri, attr, H, W, tri_id, g, append_z=False):
     L = (out * gt).sum()
     L.backward()
     return vt.grad.numpy(), at.grad.numpy()
+
+
+def interp_jvp_torch(v, tri, attr, H, W, tri_id, dv, dattr=None, append_z=False):
+    """Forward-mode tangent of the interpolated image at a fixed index image,
+    by torch.func.jvp of the continuous binary64 formulas; [H*W, C]."""
+    import torch
+    from torch.func import jvp
+
+    tid = np.asarray(tri_id)
+    pix = np.nonzero(tid >= 0)[0]
+    t = torch.tensor(np.asarray(tri)[tid[pix]].astype(np.int64))
+    Px = torch.tensor((pix % W) + 0.5, dtype=torch.float64)
+    Py = torch.tensor((pix // W) + 0.5, dtype=torch.float64)
+
+    def orient(p, q, rx, ry):
+        return (q[:, 0] - p[:, 0]) * (ry - p[:, 1]) - (q[:, 1] - p[:, 1]) * (rx - p[:, 0])
+
+    def interp(vt, at):
+        a, b, c = vt[t[:, 0]], vt[t[:, 1]], vt[t[:, 2]]
+        D = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (c[:, 0] - a[:, 0]) * (b[:, 1] - a[:, 1])
+        beta = torch.stack([orient(b, c, Px, Py), orient(c, a, Px, Py), orient(a, b, Px, Py)], 1) / D[:, None]
+        z = torch.stack([a[:, 2], b[:, 2], c[:, 2]], 1)
+        w = beta / z
+        bb = w / w.sum(1, keepdim=True)
+        out = (bb[:, :, None] * at[t]).sum(1)
+        if append_z:
+            out = torch.cat([out, (bb * z).sum(1, keepdim=True)], 1)
+        return out
+
+    vt = torch.tensor(np.asarray(v, np.float64))
+    at = torch.tensor(np.asarray(attr, np.float64))
+    dvt = torch.tensor(np.asarray(dv, np.float64))
+    dat = torch.zeros_like(at) if dattr is None else torch.tensor(np.asarray(dattr, np.float64))
+    _, d = jvp(interp, (vt, at), (dvt, dat))
+    out = np.zeros((H * W, d.shape[1]))
+    out[pix] = d.numpy()
+    return out
