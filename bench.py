@@ -161,13 +161,18 @@ def algorithmic_bytes(s, kernel):
     raise KeyError(kernel)
 
 
-def source_hash():
-    """Hash of the HIP sources, to tell whether stored counter data still
-    describes the kernels being run."""
+# HIP sources that define the backward sweep kernel (its file and the device
+# helpers it includes)
+BACKWARD_SOURCES = ("mer_backward.hip", "mer_device.h")
+
+
+def source_hash(names=BACKWARD_SOURCES):
+    """Hash of a kernel's HIP sources, to tell whether stored counter data
+    still describes the kernel being run."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2405_02508_amd", "csrc")
-    for name in sorted(os.listdir(d)):
+    for name in names:
         with open(os.path.join(d, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
