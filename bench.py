@@ -143,6 +143,34 @@ def kernel_times(st, iters, stream):
     return {k: acc[k] / iters for k in names}
 
 
+def jvp_time(st, iters, stream):
+    """Forward-mode image tangent of the step's image (mer_jvp, one call per
+    plan) for a seeded tangent of every screen vertex and attribute: average
+    call time on its stream, HIP events."""
+    import torch
+    s = st.s
+    gen = torch.Generator(device=st.dev).manual_seed(11)
+    dv = torch.randn(st.v.shape, generator=gen, device=st.dev)
+    dv[:, 2] *= 0.01 * st.v[:, 2]
+    dattr = torch.randn(st.attr.shape, generator=gen, device=st.dev)
+    dimg = torch.empty(s.n_px, s.C_e, dtype=torch.float32, device=st.dev)
+    st.forward()
+
+    def call():
+        for c in st.ctxs:
+            c.jvp(st.v, st.tri, st.tid, st.attr, st.img, dv, dimg, dattr=dattr, append_z=s.append_z)
+
+    call()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(iters):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / iters
+
+
 def algorithmic_bytes(s, kernel):
     """Bytes the method must move per launch (model stated in the design notes)."""
     n_px = s.n_px
@@ -156,6 +184,11 @@ def algorithmic_bytes(s, kernel):
     if kernel == "rasterize":
         # per view-triangle index row, per view-vertex position; write tri_id, depth (+bary)
         return view_tris * 12 + view_verts * 12 + n_px * (8 + (8 if not s.recompute else 0))
+    if kernel == "jvp":
+        # read tri_id and image, write the tangent image per pixel; per
+        # view-triangle its index row, per view-vertex position and tangent;
+        # attributes and their tangent
+        return n_px * (4 + 8 * s.C_e) + view_tris * 12 + view_verts * 24 + s.attr.size * 4 * 2
     if kernel == "interpolate":
         return n_px * (4 + (8 if not s.recompute else 0) + 4 * s.C_out) + s.attr.size * 4 + view_tris * 12
     raise KeyError(kernel)
@@ -295,6 +328,8 @@ def main():
     log(f"[bench] batched {'graph' if graph else 'eager'}: {ms:.3f} ms/step")
     kt = kernel_times(st, max(3, min(args.steps, 10)), stream)
     log(f"[bench] per-call ms: {kt}")
+    jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
+    log(f"[bench] forward-mode image tangent: {jvp_ms:.3f} ms per call")
     status = st.ctxs[0].status()
     log(f"[bench] status {status}")
 
@@ -341,6 +376,14 @@ def main():
                      "traffic": stored_traffic(args.workload, "k_backward"),
                      "algorithmic_bytes": ab, "avg_launch_ms": round(kt[dom], 4), "src_hash": source_hash()},
         "cpu_baseline": None,
+        # forward-mode image tangent of the same image (Sec. 5, forward
+        # gradients): its own call, outside the step
+        "jvp": {"kernel": "k_jvp", "ms_per_call": round(jvp_ms, 4), "value": round(s.n_px / jvp_ms / 1e3, 2),
+                "unit": "Mpx/s",
+                "roofline": {"bound": "hbm", "achieved": round(algorithmic_bytes(s, "jvp") / (jvp_ms * 1e-3) / 1e9, 1),
+                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(algorithmic_bytes(s, "jvp") / (jvp_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                             "algorithmic_bytes": algorithmic_bytes(s, "jvp")}},
     }
     if not args.no_cpu:
         del st

@@ -246,6 +246,40 @@ int mer_backward_l2(const mer_plan *plan, const mer_view *views_dev, const float
                     const float *target, float weight, int C_e, int flags, float *g_attr, float *g_v, float *loss,
                     void *ws, void *stream);
 
+/* Forward mode (Sec. 5, "Forward gradients": per-pixel derivatives of the
+ * image with respect to a scene parameter).  For a tangent dv of the screen
+ * vertices and dattr of the attributes, writes the image tangent
+ *   dimg[p, c] = interior[p, c] + edge[p, c]
+ * for every pixel p of every view (pixels in gaps between views are not
+ * written), the transpose of mer_backward_fused: for any g,
+ * sum g . dimg = (dL/dv) . dv + (dL/dattr) . dattr with dL/dv, dL/dattr what
+ * mer_backward_fused returns for dL/d(img) = g.
+ *   interior (c < C_a + append_z, unless MER_SKIP_INTERP; 0 on background
+ *   and on the channels beyond): the derivative of sum_k b_k a_kc (and of
+ *   the interpolated z) at the fixed index image, through the perspective
+ *   barycentrics b_k = (beta_k / z_k) / sum_j (beta_j / z_j), beta_k = E_k / D
+ *   (fixed-point snapping taken as the identity), plus sum_k b_k dattr_kc.
+ *   edge (all C_e channels, unless MER_SKIP_EDGE): each pair of neighbouring
+ *   pixels A (left/upper), B with different triangle ids, classified as in
+ *   mer_edge_grad, moves its edge position p by dp: an overhang's dp is the
+ *   axis component of the top fragment's tangent, sum_k beta_k dv_k with the
+ *   fragment's own screen barycentrics beta at its centre; an intersection's
+ *   dp = (-s_A dr_A + dq_A + s_B dr_B - dq_B) / (s_B - s_A), with dr the
+ *   fragments' axis tangents, dq = sum_k beta_k (-1/z_k^2) dz_k their 1/z
+ *   tangents and the pair skipped unless s_B - s_A > 0.  Both pixels of the
+ *   pair change by 1/2 (img[A,c] - img[B,c]) dp.
+ * An id naming a triangle that does not snap (culled) counts as background.
+ *   dv: float [sum n_v, 3] or NULL (no geometry tangent: only dattr acts);
+ *   dattr: float [*, C_a] like attr, or NULL.  attr is required unless
+ *   MER_SKIP_INTERP, img [total_px, C_e] unless MER_SKIP_EDGE (with dv).
+ *   dimg: float [total_px, C_e], written.  1 <= C_e <= 64; C_a + append_z
+ *   <= C_e when the interior term is on.  flags: MER_NO_INTERSECT,
+ *   MER_SKIP_EDGE, MER_SKIP_INTERP.  One thread per pixel, no atomics: the
+ *   result is deterministic.  The workspace is not used. */
+int mer_jvp(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+            const int32_t *tri_id, const float *attr, const float *dattr, int C_a, int append_z,
+            const float *img, int C_e, const float *dv, int flags, float *dimg, void *stream);
+
 /* Wait for `stream`, then read the workspace status of the last
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool
  * (they were rasterized by the slower fallback, results unchanged),

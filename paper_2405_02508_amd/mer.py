@@ -21,7 +21,7 @@ SKIP_INTERP = 4
 
 SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_rasterize_interpolate",
            "mer_interpolate", "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused",
-           "mer_backward_l2", "mer_status", "mer_strerror", "mer_version")
+           "mer_backward_l2", "mer_jvp", "mer_status", "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -82,6 +82,7 @@ def lib():
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
         L.mer_backward_l2.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P, P,
                                       P, P, P]
+        L.mer_jvp.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, i, P, i, P, P]
         L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
         L.mer_strerror.argtypes = [i]
         L.mer_strerror.restype = ctypes.c_char_p
@@ -355,6 +356,38 @@ class Context:
                                      _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
                                      _ptr(target), float(weight), int(img.shape[1]), int(flags), _ptr(g_attr),
                                      _ptr(g_v), _ptr(loss), _ptr(self.ws), _stream()))
+
+    def jvp(self, v, tri, tri_id, attr, img, dv, dimg, dattr=None, append_z=False, flags=0):
+        """Forward mode: dimg [px, C_e] = image tangent for the screen-vertex
+        tangent ``dv`` [sum n_v, 3] (or None) and attribute tangent ``dattr``
+        (like attr, or None): the interpolated channels' derivative at the
+        fixed index image plus the micro-edge term on every channel of
+        ``img``.  ``attr`` may be None with MER_SKIP_INTERP."""
+        import torch
+        _need(tri_id, torch.int32, "tri_id")
+        _need(dimg, torch.float32, "dimg")
+        self._px(tri_id, "tri_id")
+        self._px(dimg, "dimg")
+        C_e = int(dimg.shape[1])
+        C_a = 0
+        if attr is not None:
+            _need(attr, torch.float32, "attr")
+            self._geom(v, tri, attr)
+            C_a = int(attr.shape[1])
+        else:
+            self._geom(v, tri, None)
+        if img is not None:
+            _need(img, torch.float32, "img")
+            self._px(img, "img", C_e)
+        if dv is not None:
+            _need(dv, torch.float32, "dv")
+            self._rows(dv, self.need_v, "dv", 3)
+        if dattr is not None:
+            _need(dattr, torch.float32, "dattr")
+            self._rows(dattr, self.need_a, "dattr", C_a)
+        _check(lib().mer_jvp(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
+                             _ptr(attr), _ptr(dattr), C_a, int(bool(append_z)), _ptr(img), C_e, _ptr(dv),
+                             int(flags), _ptr(dimg), _stream()))
 
     def status(self):
         out = (ctypes.c_int64 * 4)()
