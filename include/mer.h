@@ -274,11 +274,12 @@ int mer_backward_l2(const mer_plan *plan, const mer_view *views_dev, const float
  *   MER_SKIP_INTERP, img [total_px, C_e] unless MER_SKIP_EDGE (with dv).
  *   dimg: float [total_px, C_e], written.  1 <= C_e <= 64; C_a + append_z
  *   <= C_e when the interior term is on.  flags: MER_NO_INTERSECT,
- *   MER_SKIP_EDGE, MER_SKIP_INTERP.  One thread per pixel, no atomics: the
- *   result is deterministic.  The workspace is not used. */
+ *   MER_SKIP_EDGE, MER_SKIP_INTERP.  One workgroup per 16x16 pixel tile,
+ *   one thread per pixel, no atomics: the result is deterministic.  Uses
+ *   the workspace's view-tile table (as the backward calls do). */
 int mer_jvp(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
             const int32_t *tri_id, const float *attr, const float *dattr, int C_a, int append_z,
-            const float *img, int C_e, const float *dv, int flags, float *dimg, void *stream);
+            const float *img, int C_e, const float *dv, int flags, float *dimg, void *ws, void *stream);
 
 /* Wait for `stream`, then read the workspace status of the last
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool

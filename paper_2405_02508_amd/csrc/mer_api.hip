@@ -213,13 +213,15 @@ int mer_backward_l2(const mer_plan* P, const mer_view* views_dev, const float* v
 
 int mer_jvp(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
             const int32_t* tri_id, const float* attr, const float* dattr, int C_a, int append_z, const float* img,
-            int C_e, const float* dv, int flags, float* dimg, void* stream) {
+            int C_e, const float* dv, int flags, float* dimg, void* ws, void* stream) {
   const int C = C_a + (append_z ? 1 : 0);
   if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !dimg || C_e < 1 || C_e > 64) return MER_EINVAL;
   if (!(flags & MER_SKIP_EDGE) && dv && !img) return MER_EINVAL;
   if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
   return mer::launch_jvp(P, views_dev, v, tri, tri_id, attr, dattr, C_a, append_z ? 1 : 0, img, C_e, dv,
-                         flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), dimg, (hipStream_t)stream);
+                         flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), dimg, ws,
+                         (hipStream_t)stream);
 }
 
 int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) {

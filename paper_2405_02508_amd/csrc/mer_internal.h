@@ -29,7 +29,7 @@ int launch_backward(const mer_plan* P, const mer_view* views, const float* v, co
 // forward-mode image tangent (flags: MER_NO_INTERSECT, MER_SKIP_EDGE, MER_SKIP_INTERP)
 int launch_jvp(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, const int32_t* tri_id,
                const float* attr, const float* dattr, int C_a, int append_z, const float* img, int C_e,
-               const float* dv, int flags, float* dimg, hipStream_t st);
+               const float* dv, int flags, float* dimg, void* ws, hipStream_t st);
 // per-view prefix tables (triangles, tiles of 2^tw_log2 x 2^th_log2) and status reset
 __global__ void __launch_bounds__(1024) k_prep(const mer_view* __restrict__ views, int n_views, int tw_log2, int th_log2,
                        long long* __restrict__ tri_base, long long* __restrict__ tile_base,

@@ -82,7 +82,7 @@ def lib():
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
         L.mer_backward_l2.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P, P,
                                       P, P, P]
-        L.mer_jvp.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, i, P, i, P, P]
+        L.mer_jvp.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, i, P, i, P, P, P]
         L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
         L.mer_strerror.argtypes = [i]
         L.mer_strerror.restype = ctypes.c_char_p
@@ -387,7 +387,7 @@ class Context:
             self._rows(dattr, self.need_a, "dattr", C_a)
         _check(lib().mer_jvp(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
                              _ptr(attr), _ptr(dattr), C_a, int(bool(append_z)), _ptr(img), C_e, _ptr(dv),
-                             int(flags), _ptr(dimg), _stream()))
+                             int(flags), _ptr(dimg), _ptr(self.ws), _stream()))
 
     def status(self):
         out = (ctypes.c_int64 * 4)()

@@ -140,11 +140,12 @@ def test_calls_reject_null_arguments_before_any_launch(L):
                              None, fake, None) == -1
     assert L.mer_backward_l2(p, fake, fake, fake, fake, fake, 3, 0, fake, fake, f(1.0), 3, 0, fake, fake, None,
                              None, None) == -2
-    # mer_jvp(plan, views, v, tri, tri_id, attr, dattr, C_a, append_z, img, C_e, dv, flags, dimg, stream)
-    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, fake, 3, fake, 0, None, None) == -1
-    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, fake, 0, fake, 0, fake, None) == -1
-    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, None, 3, fake, 0, fake, None) == -1
-    assert L.mer_jvp(p, fake, fake, fake, fake, None, None, 3, 0, fake, 3, fake, 0, fake, None) == -1
-    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 1, fake, 3, fake, 0, fake, None) == -1
+    # mer_jvp(plan, views, v, tri, tri_id, attr, dattr, C_a, append_z, img, C_e, dv, flags, dimg, ws, stream)
+    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, fake, 3, fake, 0, None, fake, None) == -1
+    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, fake, 0, fake, 0, fake, fake, None) == -1
+    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, None, 3, fake, 0, fake, fake, None) == -1
+    assert L.mer_jvp(p, fake, fake, fake, fake, None, None, 3, 0, fake, 3, fake, 0, fake, fake, None) == -1
+    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 1, fake, 3, fake, 0, fake, fake, None) == -1
+    assert L.mer_jvp(p, fake, fake, fake, fake, fake, None, 3, 0, fake, 3, fake, 0, fake, None, None) == -2
     assert L.mer_status(p, None, None, (ctypes.c_int64 * 4)()) == -2
     assert L.mer_plan_init(None, 1, None, p) == -1
