@@ -8,8 +8,9 @@ a time, in float64 unless a discrete outcome is decided (see the C file).
 Functions follow the paper's modules (supplement, "Implementation detail"):
 rasterisation -> index image, barycentrics/depth at the index image,
 interpolation and its adjoint (the smooth term Omega), the EdgeGrad
-backward (Sec. 4.2-4.4), and the forward-mode image tangents of both (Sec. 5,
-"Forward gradients").
+backward (Sec. 4.2-4.4), the forward-mode image tangents of both (Sec. 5,
+"Forward gradients"), and the bilinear texture sampler with its adjoint
+(deferred texturing of interpolated uv).
 """
 from __future__ import annotations
 
@@ -58,6 +59,8 @@ def lib():
         L.orc_interpolate_bwd.argtypes = [P, i, P, i, P, i, i, P, i, P, P, P]
         L.orc_edge_grad.argtypes = [P, i, P, i, i, P, P, P, i, i, P, P, P]
         L.orc_backface.argtypes = [P, i, P, i, i, i, P, P]
+        L.orc_texture.argtypes = [P, i, i, i, i64, P, i, P, P]
+        L.orc_texture_bwd.argtypes = [P, i, i, i, i64, P, i, P, P, P, P]
         L.orc_edge_jvp.argtypes = [P, i, P, i, i, P, P, i, i, P, P, P]
         L.orc_interpolate_jvp.argtypes = [P, i, P, P, i, P, i, i, P, i, P, P]
         _lib = L
@@ -190,6 +193,31 @@ def interpolate_jvp(attr, v, tri, H, W, tri_id, dv=None, dattr=None, append_z=Fa
     lib().orc_interpolate_jvp(_p(attr), C_a, _p(dattr), _p(v), v.shape[0], _p(tri), H, W, _p(tri_id),
                               int(append_z), _p(dv), _p(out))
     return out
+
+
+def texture(tex, uv, tri_id=None):
+    """Bilinear, clamp-to-edge samples of tex [th, tw, C] at uv [n, >=2]
+    (first two columns); 0 where tri_id < 0 or uv is not finite.  [n, C]."""
+    tex, uv = _f64(tex), _f64(uv)
+    th, tw, C = tex.shape
+    n = uv.shape[0]
+    tid = None if tri_id is None else _i32(tri_id)
+    out = np.empty((n, C))
+    lib().orc_texture(_p(tex), th, tw, C, n, _p(uv), uv.shape[1], _p(tid), _p(out))
+    return out
+
+
+def texture_bwd(tex, uv, g_out, tri_id=None):
+    """Adjoint of ``texture``: (g_tex [th, tw, C], g_uv [n, 2])."""
+    tex, uv, g_out = _f64(tex), _f64(uv), _f64(g_out)
+    th, tw, C = tex.shape
+    n = uv.shape[0]
+    assert g_out.shape == (n, C)
+    tid = None if tri_id is None else _i32(tri_id)
+    g_tex = np.zeros_like(tex)
+    g_uv = np.empty((n, 2))
+    lib().orc_texture_bwd(_p(tex), th, tw, C, n, _p(uv), uv.shape[1], _p(tid), _p(g_out), _p(g_tex), _p(g_uv))
+    return g_tex, g_uv
 
 
 # ------------------------------------------------------- whole scene (views)

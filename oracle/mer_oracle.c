@@ -29,6 +29,9 @@
  *     of an overhang, and for an intersection dp/dr from the slopes of the
  *     two planes in the (axis, 1/z) slice; then fragment gradients go to the
  *     vertices through the screen-space barycentric weights.
+ *   - the texture sampler (supplement, "Implementation detail": uv
+ *     interpolated per pixel, a neural texture sampled there): bilinear,
+ *     clamp-to-edge, and its adjoint to the texture and to uv.
  *   - forward mode (Sec. 5, "Forward gradients"): the per-pixel image tangent
  *     for a tangent of the screen vertices (and attributes), the transpose of
  *     the two reverse-mode parts above.
@@ -622,4 +625,92 @@ void orc_interpolate_jvp(const float *attr, int C_a, const double *dattr, const 
         dout[p * C + C_a] = acc;
       }
     }
+}
+
+/* ------------------------------------------------------ texture sampler */
+/* Deferred texturing (supplement, "Implementation detail": uv coordinates
+ * are interpolated per pixel and a neural texture is sampled at them; Sec. 3
+ * names the texture sampler among the parts the smooth term differentiates
+ * through).  tex[(y * tw + x) * C + c], texel (x, y) centred at
+ * ((x + 1/2) / tw, (y + 1/2) / th).  Bilinear filtering with clamp-to-edge
+ * addressing: s = u tw - 1/2 and t = v th - 1/2 (first clamped to
+ * [-1, tw] and [-1, th]), x0 = floor(s), fx = s - x0, likewise y0, fy, and
+ * the four texels (x0 + i, y0 + j), i, j in {0, 1}, each index clamped to the
+ * texture, weighted (1 - fx or fx) (1 - fy or fy).  A pixel is sampled
+ * where tri_id >= 0 (all pixels when tri_id is NULL) and its uv is finite;
+ * other pixels give 0 and take no gradient. */
+static int orc_tex_setup(const double *uvp, int th, int tw, int64_t xi[2], int64_t yi[2], double *fx,
+                         double *fy) {
+  double u = uvp[0], w = uvp[1];
+  if (!isfinite(u) || !isfinite(w)) return 0;
+  double s = u * tw - 0.5, t = w * th - 0.5;
+  if (s < -1.0) s = -1.0;
+  if (s > (double)tw) s = (double)tw;
+  if (t < -1.0) t = -1.0;
+  if (t > (double)th) t = (double)th;
+  double x0 = floor(s), y0 = floor(t);
+  *fx = s - x0;
+  *fy = t - y0;
+  for (int i = 0; i < 2; ++i) {
+    int64_t x = (int64_t)x0 + i, y = (int64_t)y0 + i;
+    xi[i] = x < 0 ? 0 : (x > tw - 1 ? tw - 1 : x);
+    yi[i] = y < 0 ? 0 : (y > th - 1 ? th - 1 : y);
+  }
+  return 1;
+}
+
+/* out[n*C] = bilinear samples; uv[n*ld_uv] holds (u, v) in its first two columns. */
+void orc_texture(const double *tex, int th, int tw, int C, int64_t n, const double *uv, int ld_uv,
+                 const int32_t *tri_id, double *out) {
+  for (int64_t p = 0; p < n; ++p) {
+    for (int c = 0; c < C; ++c) out[p * C + c] = 0.0;
+    if (tri_id && tri_id[p] < 0) continue;
+    int64_t xi[2], yi[2];
+    double fx, fy;
+    if (!orc_tex_setup(uv + p * ld_uv, th, tw, xi, yi, &fx, &fy)) continue;
+    double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy};
+    for (int j = 0; j < 2; ++j)
+      for (int i = 0; i < 2; ++i) {
+        const double *tp = tex + (yi[j] * tw + xi[i]) * C;
+        for (int c = 0; c < C; ++c) out[p * C + c] += wx[i] * wy[j] * tp[c];
+      }
+  }
+}
+
+/* Adjoint: g_tex[th*tw*C] += the transpose of the sampling applied to
+ * g_out[n*C]; g_uv[n*2] (written) = sum_c g_out[p,c] d out[p,c] / d(u, v),
+ * the derivative of the bilinear interpolant inside the cell (tw times the
+ * difference of the two horizontally neighbouring texel pairs, blended by
+ * fy, and likewise for v), 0 for pixels that are not sampled.  Either
+ * output may be NULL. */
+void orc_texture_bwd(const double *tex, int th, int tw, int C, int64_t n, const double *uv, int ld_uv,
+                     const int32_t *tri_id, const double *g_out, double *g_tex, double *g_uv) {
+  for (int64_t p = 0; p < n; ++p) {
+    if (g_uv) g_uv[2 * p] = g_uv[2 * p + 1] = 0.0;
+    if (tri_id && tri_id[p] < 0) continue;
+    int64_t xi[2], yi[2];
+    double fx, fy;
+    const double *uvp = uv + p * ld_uv;
+    if (!orc_tex_setup(uvp, th, tw, xi, yi, &fx, &fy)) continue;
+    double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy};
+    const double *g = g_out + p * C;
+    if (g_tex)
+      for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+          double *gp = g_tex + (yi[j] * tw + xi[i]) * C;
+          for (int c = 0; c < C; ++c) gp[c] += wx[i] * wy[j] * g[c];
+        }
+    if (!g_uv) continue;
+    /* where a coordinate is clamped, or in the half texel next to the edge,
+     * both texels along that axis are the same and the difference is 0 */
+    double du = 0.0, dvv = 0.0;
+    for (int c = 0; c < C; ++c) {
+      double t00 = tex[(yi[0] * tw + xi[0]) * C + c], t10 = tex[(yi[0] * tw + xi[1]) * C + c];
+      double t01 = tex[(yi[1] * tw + xi[0]) * C + c], t11 = tex[(yi[1] * tw + xi[1]) * C + c];
+      du += g[c] * (wy[0] * (t10 - t00) + wy[1] * (t11 - t01));
+      dvv += g[c] * (wx[0] * (t01 - t00) + wx[1] * (t11 - t10));
+    }
+    g_uv[2 * p] = du * tw;
+    g_uv[2 * p + 1] = dvv * th;
+  }
 }

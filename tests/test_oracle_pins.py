@@ -867,3 +867,85 @@ def test_p15_jvp_vs_finite_differences_of_supersampled_render():
             fd.append((Lp - Lm) / 1.0)
         ana, fd = np.array(ana), np.array(fd)
         assert np.linalg.norm(ana - fd) / np.linalg.norm(fd) <= _tol_from_paper(), (name, ana, fd)
+
+
+# ------------------------------------------------------ P16 texture sampler
+def _tex_case(seed, th=9, tw=13, C=3, n=400):
+    rng = np.random.default_rng(seed)
+    tex = rng.normal(size=(th, tw, C))
+    uv = rng.uniform(-0.2, 1.2, size=(n, 2))
+    return tex, uv
+
+
+def test_p16_texture_matches_torch_grid_sample():
+    """Bilinear, clamp-to-edge sampling with texel centres at (i + 1/2)/size
+    is torch's grid_sample (bilinear, border padding, align_corners=False)
+    at grid = 2 uv - 1; its adjoint is grid_sample's autograd (the grid
+    gradient times d grid / d uv = 2).  Binary64 on the CPU."""
+    import torch
+    import torch.nn.functional as F
+    tex, uv = _tex_case(1)
+    g = np.random.default_rng(2).normal(size=(uv.shape[0], tex.shape[2]))
+    out = oracle.texture(tex, uv)
+    g_tex, g_uv = oracle.texture_bwd(tex, uv, g)
+    T = torch.tensor(tex.transpose(2, 0, 1)[None].copy(), requires_grad=True)      # [1, C, th, tw]
+    G = torch.tensor((2 * uv - 1)[None, :, None, :].copy(), requires_grad=True)    # [1, n, 1, 2]
+    ref = F.grid_sample(T, G, mode="bilinear", padding_mode="border", align_corners=False)  # [1, C, n, 1]
+    ref_out = ref[0, :, :, 0].T.detach().numpy()
+    np.testing.assert_allclose(out, ref_out, rtol=1e-12, atol=1e-12)
+    (ref[0, :, :, 0].T * torch.tensor(g)).sum().backward()
+    np.testing.assert_allclose(g_tex, T.grad[0].numpy().transpose(1, 2, 0), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(g_uv, 2 * G.grad[0, :, 0, :].numpy(), rtol=1e-10, atol=1e-10)
+
+
+def test_p16_linear_texture_is_reproduced_exactly():
+    """A texture linear in the texel index is interpolated exactly inside the
+    texel-centre grid, and its uv gradient is the slope times the size."""
+    th, tw = 11, 17
+    y, x = np.mgrid[0:th, 0:tw].astype(np.float64)
+    a, b, d = np.array([0.3, -1.2]), np.array([2.0, 0.5]), np.array([1.0, -3.0])
+    tex = x[..., None] * a + y[..., None] * b + d
+    rng = np.random.default_rng(3)
+    s = rng.uniform(0, tw - 1, 300)
+    t = rng.uniform(0, th - 1, 300)
+    uv = np.stack([(s + 0.5) / tw, (t + 0.5) / th], 1)
+    out = oracle.texture(tex, uv)
+    np.testing.assert_allclose(out, s[:, None] * a + t[:, None] * b + d, rtol=1e-12, atol=1e-12)
+    g = np.zeros((300, 2))
+    g[:, 0] = 1.0
+    _, g_uv = oracle.texture_bwd(tex, uv, g)
+    np.testing.assert_allclose(g_uv, np.tile([a[0] * tw, b[0] * th], (300, 1)), rtol=1e-12)
+    # texel centres return the texel itself
+    cx, cy = rng.integers(0, tw, 50), rng.integers(0, th, 50)
+    uvc = np.stack([(cx + 0.5) / tw, (cy + 0.5) / th], 1)
+    np.testing.assert_allclose(oracle.texture(tex, uvc), tex[cy, cx], rtol=1e-14, atol=1e-14)
+
+
+def test_p16_texture_adjoint_and_masking():
+    """Sampling is linear in the texture: <G, S(tex)> = <S^T G, tex>.  Pixels
+    with tri_id < 0 or a non-finite uv read 0 and take no gradient; the
+    uv gradient matches central differences away from texel-centre lines."""
+    tex, uv = _tex_case(4)
+    n, C = uv.shape[0], tex.shape[2]
+    rng = np.random.default_rng(5)
+    G = rng.normal(size=(n, C))
+    g_tex, g_uv = oracle.texture_bwd(tex, uv, G)
+    assert abs((G * oracle.texture(tex, uv)).sum() - (g_tex * tex).sum()) < 1e-10
+    tid = np.where(rng.uniform(size=n) < 0.3, -1, 5).astype(np.int32)
+    uv2 = uv.copy()
+    uv2[7] = [np.nan, 0.5]
+    uv2[9] = [0.5, np.inf]
+    out = oracle.texture(tex, uv2, tid)
+    gt, gu = oracle.texture_bwd(tex, uv2, G, tid)
+    dead = (tid < 0) | ~np.isfinite(uv2).all(1)
+    assert np.all(out[dead] == 0) and np.all(gu[dead] == 0)
+    live = ~dead
+    np.testing.assert_allclose(out[live], oracle.texture(tex, uv2[live]))
+    gt_ref, _ = oracle.texture_bwd(tex, uv2[live], G[live])
+    np.testing.assert_allclose(gt, gt_ref, rtol=1e-12, atol=1e-12)
+    h = 1e-7
+    for k in range(2):
+        e = np.zeros(2)
+        e[k] = h
+        fd = ((oracle.texture(tex, uv + e) - oracle.texture(tex, uv - e)) * G).sum(1) / (2 * h)
+        np.testing.assert_allclose(g_uv[:, k], fd, rtol=1e-5, atol=1e-5 * np.abs(fd).max())
