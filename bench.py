@@ -171,7 +171,50 @@ def jvp_time(st, iters, stream):
     return e0.elapsed_time(e1) / iters
 
 
-def algorithmic_bytes(s, kernel):
+def texture_time(st, iters, stream, size=1024, channels=8):
+    """Deferred texturing on the step's pixels: uv interpolated from seeded
+    per-vertex uv, an 8-channel 1024^2 texture (the paper's neural texture)
+    sampled, then its adjoint to the texture and uv.  Average call times on
+    the stream, HIP events."""
+    import torch
+
+    from paper_2405_02508_amd import scenes
+    s = st.s
+    uv_attr, tex = scenes.texture_inputs(s, 1, size=size, channels=channels)
+    ua = torch.from_numpy(uv_attr).to(st.dev)
+    texd = torch.from_numpy(tex).to(st.dev)
+    uvp = torch.empty(s.n_px, 2, dtype=torch.float32, device=st.dev)
+    out = torch.empty(s.n_px, channels, dtype=torch.float32, device=st.dev)
+    g = torch.randn(s.n_px, channels, generator=torch.Generator(device=st.dev).manual_seed(5), device=st.dev)
+    g_tex = torch.zeros_like(texd)
+    g_uv = torch.empty(s.n_px, 2, dtype=torch.float32, device=st.dev)
+    st.forward()
+    for c in st.ctxs:
+        c.interpolate(ua, st.v, st.tri, st.tid, uvp, bary=None, append_z=False)
+
+    def fwd():
+        for c in st.ctxs:
+            c.texture(st.tid, uvp, texd, out)
+
+    def bwd():
+        for c in st.ctxs:
+            c.texture_bwd(st.tid, uvp, texd, g, g_tex, g_uv)
+
+    res = {}
+    for name, fn in (("forward", fwd), ("backward", bwd)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(iters):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / iters
+    return res
+
+
+def algorithmic_bytes(s, kernel, channels=8, tex_bytes=1024 * 1024 * 8 * 4):
     """Bytes the method must move per launch (model stated in the design notes)."""
     n_px = s.n_px
     V = s.views
@@ -189,6 +232,13 @@ def algorithmic_bytes(s, kernel):
         # view-triangle its index row, per view-vertex position and tangent;
         # attributes and their tangent
         return n_px * (4 + 8 * s.C_e) + view_tris * 12 + view_verts * 24 + s.attr.size * 4 * 2
+    if kernel == "texture":
+        # read tri_id and uv, write the samples; the texture once
+        return n_px * (4 + 8 + 4 * channels) + tex_bytes
+    if kernel == "texture_bwd":
+        # read tri_id, uv and dL/d(out), write dL/duv; texture read once,
+        # its gradient read and written once
+        return n_px * (4 + 8 + 4 * channels + 8) + 3 * tex_bytes
     if kernel == "interpolate":
         return n_px * (4 + (8 if not s.recompute else 0) + 4 * s.C_out) + s.attr.size * 4 + view_tris * 12
     raise KeyError(kernel)
@@ -330,6 +380,8 @@ def main():
     log(f"[bench] per-call ms: {kt}")
     jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
     log(f"[bench] forward-mode image tangent: {jvp_ms:.3f} ms per call")
+    tex_ms = texture_time(st, max(3, min(args.steps, 10)), stream)
+    log(f"[bench] texture sampler 1024^2 x 8: {tex_ms}")
     status = st.ctxs[0].status()
     log(f"[bench] status {status}")
 
@@ -384,6 +436,16 @@ def main():
                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(algorithmic_bytes(s, "jvp") / (jvp_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                              "algorithmic_bytes": algorithmic_bytes(s, "jvp")}},
+        # deferred texturing of the same pixels: an 8-channel 1024^2 texture
+        # sampled at interpolated uv, and its adjoint (texture and uv)
+        "texture": {"kernels": ["k_texture", "k_texture_bwd"], "texture": [1024, 1024, 8],
+                    "ms_forward": round(tex_ms["forward"], 4), "ms_backward": round(tex_ms["backward"], 4),
+                    "roofline_forward": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                         "achieved": round(algorithmic_bytes(s, "texture") / (tex_ms["forward"] * 1e-3) / 1e9, 1),
+                                         "algorithmic_bytes": algorithmic_bytes(s, "texture")},
+                    "roofline_backward": {"bound": "atomics", "peak": None, "unit": "GB/s",
+                                          "achieved": round(algorithmic_bytes(s, "texture_bwd") / (tex_ms["backward"] * 1e-3) / 1e9, 1),
+                                          "algorithmic_bytes": algorithmic_bytes(s, "texture_bwd")}},
     }
     if not args.no_cpu:
         del st

@@ -281,6 +281,41 @@ int mer_jvp(const mer_plan *plan, const mer_view *views_dev, const float *v, con
             const int32_t *tri_id, const float *attr, const float *dattr, int C_a, int append_z,
             const float *img, int C_e, const float *dv, int flags, float *dimg, void *ws, void *stream);
 
+/* Texture sampler (supplement, "Implementation detail": uv coordinates are
+ * interpolated per pixel, then a neural texture is sampled at them in a
+ * deferred shading step; Sec. 3 lists the texture sampler among the parts
+ * the smooth term differentiates through).  Bilinear filtering with
+ * clamp-to-edge addressing: texel (x, y) of the tex_h x tex_w texture is
+ * centred at ((x + 1/2) / tex_w, (y + 1/2) / tex_h); s = u tex_w - 1/2 and
+ * t = v tex_h - 1/2 (formed in binary64, clamped to [-1, tex_w] and
+ * [-1, tex_h]), x0 = floor(s), fx = s - x0, likewise y0, fy; texels
+ * (x0 + i, y0 + j), i, j in {0, 1}, each index clamped into the texture,
+ * weighted (1 - fx or fx)(1 - fy or fy).  A pixel is sampled where
+ * tri_id >= 0 (every pixel when tri_id is NULL) and its uv is finite; other
+ * pixels of the views get 0 (gaps between views are not written).
+ *   uv: float, row p holds (u, v) in its first two of ld_uv >= 2 columns
+ *   (so it can be a slice of an interpolated image).  tex: float
+ *   [tex_h, tex_w, C_t], channels last, 1 <= C_t <= 64.  out: float
+ *   [total_px, C_t], written.  The workspace is not used. */
+int mer_texture(const mer_plan *plan, const mer_view *views_dev, const int32_t *tri_id, const float *uv,
+                int ld_uv, const float *tex, int tex_h, int tex_w, int C_t, float *out, void *stream);
+
+/* Adjoint of mer_texture for dL/d(out) g_out [total_px, C_t]:
+ *   g_tex [tex_h, tex_w, C_t] += the transpose of the sampling (each sampled
+ *   pixel adds weight * g_out to its four texels; a workgroup sums its 16x16
+ *   pixels' contributions in LDS when the box of texels they touch holds at
+ *   most 6144 values, else adds them straight to memory with float atomics);
+ *   g_uv [total_px, 2] (written, every pixel of the views) = sum_c g_out[p,c]
+ *   d out[p,c] / d(u, v) inside the texel cell: tex_w times the fy-blend of
+ *   the two horizontal texel differences, tex_h times the fx-blend of the two
+ *   vertical ones (0 where a coordinate is clamped, and for pixels that are
+ *   not sampled).  g_uv then feeds mer_interpolate_bwd as the gradient of the
+ *   interpolated uv.  Either output may be NULL.  Uses the workspace's
+ *   view-tile table. */
+int mer_texture_bwd(const mer_plan *plan, const mer_view *views_dev, const int32_t *tri_id, const float *uv,
+                    int ld_uv, const float *tex, int tex_h, int tex_w, int C_t, const float *g_out, float *g_tex,
+                    float *g_uv, void *ws, void *stream);
+
 /* Wait for `stream`, then read the workspace status of the last
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool
  * (they were rasterized by the slower fallback, results unchanged),

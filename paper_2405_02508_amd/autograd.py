@@ -122,6 +122,40 @@ class EdgeGrad(torch.autograd.Function):
         return g_img, g_v, None, None, None
 
 
+class Texture(torch.autograd.Function):
+    """Deferred texturing: bilinear clamp-to-edge samples of tex [th, tw, C]
+    at per-pixel uv (the first two columns of ``uv``, e.g. an interpolated
+    uv attribute); 0 on background.  Backward: to the texture and to uv
+    (whose gradient then flows through Interpolate to the uv attribute and,
+    through the barycentrics, to the vertices)."""
+
+    @staticmethod
+    def forward(ctx, uv, tex, tid, r: Renderer):
+        uvc = uv.detach()
+        if uvc.stride(1) != 1:
+            uvc = uvc.contiguous()
+        texc = tex.detach().contiguous()
+        out = torch.empty(r.n_px, tex.shape[2], dtype=torch.float32, device=uv.device)
+        r.ctx.texture(tid, uvc, texc, out)
+        ctx.save_for_backward(uvc, texc, tid)
+        ctx.r = r
+        ctx.mark_non_differentiable(tid)
+        return out
+
+    @staticmethod
+    def backward(ctx, g_out):
+        uv, tex, tid = ctx.saved_tensors
+        g_tex = torch.zeros_like(tex) if ctx.needs_input_grad[1] else None
+        g_uv2 = torch.empty(uv.shape[0], 2, dtype=torch.float32, device=uv.device) if ctx.needs_input_grad[0] else None
+        if g_tex is not None or g_uv2 is not None:
+            ctx.r.ctx.texture_bwd(tid, uv, tex, g_out.contiguous(), g_tex, g_uv2)
+        g_uv = None
+        if g_uv2 is not None:
+            g_uv = torch.zeros(uv.shape, dtype=torch.float32, device=uv.device)
+            g_uv[:, :2] = g_uv2
+        return g_uv, g_tex, None, None
+
+
 class RenderStep(torch.autograd.Function):
     """One call per step: image = [interpolated attributes (+ z), (mask)] with
     the EdgeGrad identity folded in; backward = one fused sweep."""

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["mer_api.hip", "mer_raster.hip", "mer_backward.hip", "mer_transform.hip", "mer_jvp.hip"]
+SOURCES = ["mer_api.hip", "mer_raster.hip", "mer_backward.hip", "mer_transform.hip", "mer_jvp.hip", "mer_texture.hip"]
 OUT = os.path.join(HERE, "libmer.so")
 
 FLAGS = [

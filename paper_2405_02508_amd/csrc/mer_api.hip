@@ -224,6 +224,26 @@ int mer_jvp(const mer_plan* P, const mer_view* views_dev, const float* v, const 
                          (hipStream_t)stream);
 }
 
+int mer_texture(const mer_plan* P, const mer_view* views_dev, const int32_t* tri_id, const float* uv, int ld_uv,
+                const float* tex, int tex_h, int tex_w, int C_t, float* out, void* stream) {
+  if (!plan_ok(P) || !views_dev || !uv || !tex || !out || ld_uv < 2 || tex_h < 1 || tex_w < 1 || C_t < 1 ||
+      C_t > 64)
+    return MER_EINVAL;
+  return mer::launch_texture(P, views_dev, tri_id, uv, ld_uv, tex, tex_h, tex_w, C_t, out, (hipStream_t)stream);
+}
+
+int mer_texture_bwd(const mer_plan* P, const mer_view* views_dev, const int32_t* tri_id, const float* uv, int ld_uv,
+                    const float* tex, int tex_h, int tex_w, int C_t, const float* g_out, float* g_tex, float* g_uv,
+                    void* ws, void* stream) {
+  if (!plan_ok(P) || !views_dev || !uv || !tex || !g_out || ld_uv < 2 || tex_h < 1 || tex_w < 1 || C_t < 1 ||
+      C_t > 64)
+    return MER_EINVAL;
+  if (!ws) return MER_EWORKSPACE;
+  if (!g_tex && !g_uv) return MER_OK;
+  return mer::launch_texture_bwd(P, views_dev, tri_id, uv, ld_uv, tex, tex_h, tex_w, C_t, g_out, g_tex, g_uv, ws,
+                                 (hipStream_t)stream);
+}
+
 int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) {
   if (!plan_ok(P) || !out) return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;

@@ -30,6 +30,12 @@ int launch_backward(const mer_plan* P, const mer_view* views, const float* v, co
 int launch_jvp(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, const int32_t* tri_id,
                const float* attr, const float* dattr, int C_a, int append_z, const float* img, int C_e,
                const float* dv, int flags, float* dimg, void* ws, hipStream_t st);
+// bilinear clamp-to-edge texture sampling and its adjoint
+int launch_texture(const mer_plan* P, const mer_view* views, const int32_t* tri_id, const float* uv, int ld_uv,
+                   const float* tex, int th, int tw, int C, float* out, hipStream_t st);
+int launch_texture_bwd(const mer_plan* P, const mer_view* views, const int32_t* tri_id, const float* uv, int ld_uv,
+                       const float* tex, int th, int tw, int C, const float* g_out, float* g_tex, float* g_uv,
+                       void* ws, hipStream_t st);
 // per-view prefix tables (triangles, tiles of 2^tw_log2 x 2^th_log2) and status reset
 __global__ void __launch_bounds__(1024) k_prep(const mer_view* __restrict__ views, int n_views, int tw_log2, int th_log2,
                        long long* __restrict__ tri_base, long long* __restrict__ tile_base,

@@ -1,0 +1,198 @@
+// mer_texture.hip -- deferred texturing: a texture sampled at per-pixel uv
+// coordinates (which the interpolator produces from per-vertex uv), and its
+// adjoint to the texture and to uv (supplement, "Implementation detail":
+// uv interpolated per pixel, then a neural texture sampled in a deferred
+// shading step; Sec. 3 lists the texture sampler among the parts the smooth
+// term differentiates through).
+//
+// Bilinear filtering, clamp-to-edge addressing.  Texel (x, y) of a th x tw
+// texture is centred at ((x + 1/2) / tw, (y + 1/2) / th); s = u tw - 1/2 and
+// t = v th - 1/2 are clamped to [-1, tw] and [-1, th], x0 = floor(s),
+// fx = s - x0 (likewise y0, fy), and texels (x0 + i, y0 + j) are read with
+// each index clamped into the texture.
+#include "mer_internal.h"
+
+namespace mer {
+
+struct TexCell {
+  int x[2], y[2];  // clamped texel indices
+  float fx, fy;
+  bool ok;         // sampled (covered pixel, finite uv)
+};
+
+// want == false gives an unsampled cell (indices 0).  The texel coordinate
+// is formed in binary64: u * tw for tw ~ 1000 would otherwise lose the
+// fraction's low bits (binary32 spacing 2^-14 at 1000).
+__device__ __forceinline__ TexCell tex_cell(bool want, float u, float v, int th, int tw) {
+  TexCell c;
+  c.ok = want && isfinite(u) && isfinite(v);
+  double s = c.ok ? (double)u * (double)tw - 0.5 : 0.0;
+  double t = c.ok ? (double)v * (double)th - 0.5 : 0.0;
+  s = fmin(fmax(s, -1.0), (double)tw);
+  t = fmin(fmax(t, -1.0), (double)th);
+  const double x0 = floor(s), y0 = floor(t);
+  c.fx = (float)(s - x0);
+  c.fy = (float)(t - y0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    c.x[i] = c.ok ? min(max((int)x0 + i, 0), tw - 1) : 0;
+    c.y[i] = c.ok ? min(max((int)y0 + i, 0), th - 1) : 0;
+  }
+  return c;
+}
+
+// Pixel p's view (searched once per wave, then per lane only across a view
+// end) and whether p lies inside it (not in a gap between views).
+__device__ __forceinline__ bool pixel_in_view(const mer_view* views, int n_views, long long p, int wvi) {
+  int vi = wvi;
+  if (vi + 1 < n_views && p >= views[vi + 1].px_off) vi = find_view_px(views, n_views, p);
+  const mer_view& vw = views[vi];
+  const long long local = p - vw.px_off;
+  return local >= 0 && local < (long long)vw.H * vw.W;
+}
+
+// ---------------------------------------------------------------- forward
+// One thread per pixel: out[p, :] = bilinear sample, or 0.
+__global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ views, int n_views,
+                                                 const int32_t* __restrict__ tri_id, const float* __restrict__ uv,
+                                                 int ld_uv, const float* __restrict__ tex, int th, int tw, int C,
+                                                 float* __restrict__ out, long long px_begin, long long total_px) {
+  const long long p = px_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int wvi = wave_view(views, n_views, p - (threadIdx.x & 63));
+  if (p >= total_px || !pixel_in_view(views, n_views, p, wvi)) return;
+  float* o = out + p * C;
+  const bool want = !tri_id || tri_id[p] >= 0;
+  const TexCell cell = tex_cell(want, want ? uv[p * ld_uv] : 0.f, want ? uv[p * ld_uv + 1] : 0.f, th, tw);
+  if (!cell.ok) {
+    for (int c = 0; c < C; ++c) o[c] = 0.f;
+    return;
+  }
+  const float w00 = (1.0f - cell.fx) * (1.0f - cell.fy), w10 = cell.fx * (1.0f - cell.fy);
+  const float w01 = (1.0f - cell.fx) * cell.fy, w11 = cell.fx * cell.fy;
+  const float* t00 = tex + ((long long)cell.y[0] * tw + cell.x[0]) * C;
+  const float* t10 = tex + ((long long)cell.y[0] * tw + cell.x[1]) * C;
+  const float* t01 = tex + ((long long)cell.y[1] * tw + cell.x[0]) * C;
+  const float* t11 = tex + ((long long)cell.y[1] * tw + cell.x[1]) * C;
+  for (int c = 0; c < C; ++c) o[c] = (w00 * t00[c] + w10 * t10[c]) + (w01 * t01[c] + w11 * t11[c]);
+}
+
+// --------------------------------------------------------------- backward
+// One workgroup per 16x16 pixel tile of one view.  g_uv is written per
+// pixel.  The texture gradient is summed in LDS over the box of texels the
+// tile touches when that box holds at most kTexWin values (then one global
+// atomic per touched texel channel), else added straight to memory.
+constexpr int kTexWin = 6144;
+
+__global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict__ views, int n_views,
+                                                     const long long* __restrict__ btile_base,
+                                                     const int32_t* __restrict__ tri_id,
+                                                     const float* __restrict__ uv, int ld_uv,
+                                                     const float* __restrict__ tex, int th, int tw, int C,
+                                                     const float* __restrict__ g_out, float* __restrict__ g_tex,
+                                                     float* __restrict__ g_uv) {
+  __shared__ float s_acc[kTexWin];
+  __shared__ int s_box[4];  // x min, y min, -x max, -y max
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
+  const mer_view vw = views[vi];
+  const long long local_tile = (long long)blockIdx.x - btile_base[vi];
+  const int tiles_x = (vw.W + 15) >> 4;
+  const int px = (int)(local_tile % tiles_x) * 16 + (threadIdx.x & 15);
+  const int py = (int)(local_tile / tiles_x) * 16 + (threadIdx.x >> 4);
+  const bool inside = px < vw.W && py < vw.H;
+  const long long p = vw.px_off + (long long)py * vw.W + px;
+  if (threadIdx.x < 4) s_box[threadIdx.x] = 0x7fffffff;
+
+  const bool want = inside && (!tri_id || tri_id[p] >= 0);
+  const TexCell cell = tex_cell(want, want ? uv[p * ld_uv] : 0.f, want ? uv[p * ld_uv + 1] : 0.f, th, tw);
+  const float* g = g_out + (cell.ok ? p : 0) * C;
+  const float w00 = (1.0f - cell.fx) * (1.0f - cell.fy), w10 = cell.fx * (1.0f - cell.fy);
+  const float w01 = (1.0f - cell.fx) * cell.fy, w11 = cell.fx * cell.fy;
+  const long long r00 = ((long long)cell.y[0] * tw + cell.x[0]) * C, r10 = ((long long)cell.y[0] * tw + cell.x[1]) * C;
+  const long long r01 = ((long long)cell.y[1] * tw + cell.x[0]) * C, r11 = ((long long)cell.y[1] * tw + cell.x[1]) * C;
+
+  if (g_uv && inside) {
+    float du = 0.f, dv = 0.f;
+    if (cell.ok) {
+      for (int c = 0; c < C; ++c) {
+        const float t00 = tex[r00 + c], t10 = tex[r10 + c], t01 = tex[r01 + c], t11 = tex[r11 + c];
+        du += g[c] * ((1.0f - cell.fy) * (t10 - t00) + cell.fy * (t11 - t01));
+        dv += g[c] * ((1.0f - cell.fx) * (t01 - t00) + cell.fx * (t11 - t10));
+      }
+    }
+    g_uv[2 * p] = du * (float)tw;
+    g_uv[2 * p + 1] = dv * (float)th;
+  }
+  if (!g_tex) return;  // uniform: every thread leaves before the barriers
+
+  __syncthreads();  // s_box initialised
+  if (cell.ok) {
+    atomicMin(&s_box[0], cell.x[0]);
+    atomicMin(&s_box[1], cell.y[0]);
+    atomicMin(&s_box[2], -cell.x[1]);
+    atomicMin(&s_box[3], -cell.y[1]);
+  }
+  __syncthreads();
+  const int bx0 = s_box[0], by0 = s_box[1];
+  const bool any = bx0 != 0x7fffffff;
+  const long long bw = any ? (long long)(-s_box[2]) - bx0 + 1 : 0, bh = any ? (long long)(-s_box[3]) - by0 + 1 : 0;
+  const long long nwin = bw * bh * C;
+  if (!any) return;  // uniform
+  if (nwin > kTexWin) {
+    if (cell.ok)
+      for (int c = 0; c < C; ++c) {
+        const float gc = g[c];
+        if (gc == 0.f) continue;
+        atomicAdd(g_tex + r00 + c, w00 * gc);
+        atomicAdd(g_tex + r10 + c, w10 * gc);
+        atomicAdd(g_tex + r01 + c, w01 * gc);
+        atomicAdd(g_tex + r11 + c, w11 * gc);
+      }
+    return;
+  }
+  for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) s_acc[i] = 0.f;
+  __syncthreads();
+  if (cell.ok) {
+    const int l00 = (int)(((cell.y[0] - by0) * bw + (cell.x[0] - bx0)) * C);
+    const int l10 = (int)(((cell.y[0] - by0) * bw + (cell.x[1] - bx0)) * C);
+    const int l01 = (int)(((cell.y[1] - by0) * bw + (cell.x[0] - bx0)) * C);
+    const int l11 = (int)(((cell.y[1] - by0) * bw + (cell.x[1] - bx0)) * C);
+    for (int c = 0; c < C; ++c) {
+      const float gc = g[c];
+      atomicAdd(&s_acc[l00 + c], w00 * gc);
+      atomicAdd(&s_acc[l10 + c], w10 * gc);
+      atomicAdd(&s_acc[l01 + c], w01 * gc);
+      atomicAdd(&s_acc[l11 + c], w11 * gc);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) {
+    const float x = s_acc[i];
+    if (x == 0.f) continue;
+    const int c = i % C, cell_i = i / C;
+    const long long ty = by0 + cell_i / bw, tx = bx0 + cell_i % bw;
+    atomicAdd(g_tex + (ty * tw + tx) * C + c, x);
+  }
+}
+
+int launch_texture(const mer_plan* P, const mer_view* views, const int32_t* tri_id, const float* uv, int ld_uv,
+                   const float* tex, int th, int tw, int C, float* out, hipStream_t st) {
+  const long long n = P->total_px - P->px_begin;
+  if (n > 0)
+    hipLaunchKernelGGL(k_texture, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views, tri_id, uv,
+                       ld_uv, tex, th, tw, C, out, P->px_begin, P->total_px);
+  return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
+}
+
+int launch_texture_bwd(const mer_plan* P, const mer_view* views, const int32_t* tri_id, const float* uv, int ld_uv,
+                       const float* tex, int th, int tw, int C, const float* g_out, float* g_tex, float* g_uv,
+                       void* ws, hipStream_t st) {
+  long long* tab = (long long*)((char*)ws + P->off_bviewtab);
+  hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, 4, 4, tab, tab + (P->n_views + 1),
+                     (long long*)nullptr);
+  if (P->total_btiles > 0)
+    hipLaunchKernelGGL(k_texture_bwd, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
+                       tab + (P->n_views + 1), tri_id, uv, ld_uv, tex, th, tw, C, g_out, g_tex, g_uv);
+  return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
+}
+
+}  // namespace mer

@@ -21,7 +21,7 @@ SKIP_INTERP = 4
 
 SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_rasterize_interpolate",
            "mer_interpolate", "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused",
-           "mer_backward_l2", "mer_jvp", "mer_status", "mer_strerror", "mer_version")
+           "mer_backward_l2", "mer_jvp", "mer_texture", "mer_texture_bwd", "mer_status", "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -83,6 +83,8 @@ def lib():
         L.mer_backward_l2.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P, P,
                                       P, P, P]
         L.mer_jvp.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, i, P, i, P, P, P]
+        L.mer_texture.argtypes = [ctypes.POINTER(Plan), P, P, P, i, P, i, i, i, P, P]
+        L.mer_texture_bwd.argtypes = [ctypes.POINTER(Plan), P, P, P, i, P, i, i, i, P, P, P, P, P]
         L.mer_status.argtypes = [ctypes.POINTER(Plan), P, P, ctypes.POINTER(i64)]
         L.mer_strerror.argtypes = [i]
         L.mer_strerror.restype = ctypes.c_char_p
@@ -388,6 +390,50 @@ class Context:
         _check(lib().mer_jvp(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri), _ptr(tri_id),
                              _ptr(attr), _ptr(dattr), C_a, int(bool(append_z)), _ptr(img), C_e, _ptr(dv),
                              int(flags), _ptr(dimg), _ptr(self.ws), _stream()))
+
+    def _tex_args(self, tri_id, uv, tex):
+        import torch
+        if tri_id is not None:
+            _need(tri_id, torch.int32, "tri_id")
+            self._px(tri_id, "tri_id")
+        if uv is None or uv.dtype != torch.float32 or not uv.is_cuda or uv.dim() != 2 or uv.shape[1] < 2 \
+                or uv.stride(1) != 1:
+            raise MerError("uv must be a float32 CUDA tensor [px, >= 2] with unit column stride")
+        if uv.shape[0] < self.n_px:
+            raise MerError(f"uv has {uv.shape[0]} rows; needs {self.n_px}")
+        _need(tex, torch.float32, "tex")
+        if tex.dim() != 3:
+            raise MerError("tex must be [tex_h, tex_w, C_t]")
+        return int(uv.stride(0)), int(tex.shape[0]), int(tex.shape[1]), int(tex.shape[2])
+
+    def texture(self, tri_id, uv, tex, out):
+        """out [px, C_t] = bilinear clamp-to-edge samples of tex [th, tw, C_t]
+        at uv (the first two columns of a [px, >= 2] tensor, e.g. a slice of
+        an interpolated image); 0 where tri_id < 0 (tri_id may be None)."""
+        import torch
+        ld, th, tw, C = self._tex_args(tri_id, uv, tex)
+        _need(out, torch.float32, "out")
+        self._px(out, "out", C)
+        _check(lib().mer_texture(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(tri_id), _ptr(uv), ld,
+                                 _ptr(tex), th, tw, C, _ptr(out), _stream()))
+
+    def texture_bwd(self, tri_id, uv, tex, g_out, g_tex=None, g_uv=None):
+        """g_tex [th, tw, C_t] += adjoint to the texture; g_uv [px, 2]
+        (written) = gradient to uv.  Either may be None."""
+        import torch
+        ld, th, tw, C = self._tex_args(tri_id, uv, tex)
+        _need(g_out, torch.float32, "g_out")
+        self._px(g_out, "g_out", C)
+        if g_tex is not None:
+            _need(g_tex, torch.float32, "g_tex")
+            if tuple(g_tex.shape) != (th, tw, C):
+                raise MerError("g_tex must have the texture's shape")
+        if g_uv is not None:
+            _need(g_uv, torch.float32, "g_uv")
+            self._px(g_uv, "g_uv", 2)
+        _check(lib().mer_texture_bwd(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(tri_id), _ptr(uv), ld,
+                                     _ptr(tex), th, tw, C, _ptr(g_out), _ptr(g_tex), _ptr(g_uv), _ptr(self.ws),
+                                     _stream()))
 
     def status(self):
         out = (ctypes.c_int64 * 4)()
