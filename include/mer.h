@@ -310,8 +310,8 @@ int mer_texture(const mer_plan *plan, const mer_view *views_dev, const int32_t *
  *   the two horizontal texel differences, tex_h times the fx-blend of the two
  *   vertical ones (0 where a coordinate is clamped, and for pixels that are
  *   not sampled).  g_uv then feeds mer_interpolate_bwd as the gradient of the
- *   interpolated uv.  Either output may be NULL.  Uses the workspace's
- *   view-tile table. */
+ *   interpolated uv.  Either output may be NULL.  tex_h * tex_w must not
+ *   exceed 2^31 - 1.  Uses the workspace's view-tile table. */
 int mer_texture_bwd(const mer_plan *plan, const mer_view *views_dev, const int32_t *tri_id, const float *uv,
                     int ld_uv, const float *tex, int tex_h, int tex_w, int C_t, const float *g_out, float *g_tex,
                     float *g_uv, void *ws, void *stream);

@@ -236,7 +236,7 @@ int mer_texture_bwd(const mer_plan* P, const mer_view* views_dev, const int32_t*
                     const float* tex, int tex_h, int tex_w, int C_t, const float* g_out, float* g_tex, float* g_uv,
                     void* ws, void* stream) {
   if (!plan_ok(P) || !views_dev || !uv || !tex || !g_out || ld_uv < 2 || tex_h < 1 || tex_w < 1 || C_t < 1 ||
-      C_t > 64)
+      C_t > 64 || (long long)tex_h * tex_w > 2147483647ll)
     return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
   if (!g_tex && !g_uv) return MER_OK;

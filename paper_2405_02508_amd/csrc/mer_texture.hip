@@ -52,7 +52,10 @@ __device__ __forceinline__ bool pixel_in_view(const mer_view* views, int n_views
 }
 
 // ---------------------------------------------------------------- forward
-// One thread per pixel: out[p, :] = bilinear sample, or 0.
+// One thread per pixel: out[p, :] = bilinear sample, or 0.  V4: C is a
+// multiple of 4 and tex, out are 16-byte aligned, so texel rows and output
+// rows move as float4.
+template <bool V4>
 __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ views, int n_views,
                                                  const int32_t* __restrict__ tri_id, const float* __restrict__ uv,
                                                  int ld_uv, const float* __restrict__ tex, int th, int tw, int C,
@@ -64,7 +67,11 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
   const bool want = !tri_id || tri_id[p] >= 0;
   const TexCell cell = tex_cell(want, want ? uv[p * ld_uv] : 0.f, want ? uv[p * ld_uv + 1] : 0.f, th, tw);
   if (!cell.ok) {
-    for (int c = 0; c < C; ++c) o[c] = 0.f;
+    if constexpr (V4) {
+      for (int c = 0; c < C; c += 4) *reinterpret_cast<float4*>(o + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      for (int c = 0; c < C; ++c) o[c] = 0.f;
+    }
     return;
   }
   const float w00 = (1.0f - cell.fx) * (1.0f - cell.fy), w10 = cell.fx * (1.0f - cell.fy);
@@ -73,7 +80,20 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
   const float* t10 = tex + ((long long)cell.y[0] * tw + cell.x[1]) * C;
   const float* t01 = tex + ((long long)cell.y[1] * tw + cell.x[0]) * C;
   const float* t11 = tex + ((long long)cell.y[1] * tw + cell.x[1]) * C;
-  for (int c = 0; c < C; ++c) o[c] = (w00 * t00[c] + w10 * t10[c]) + (w01 * t01[c] + w11 * t11[c]);
+  if constexpr (V4) {
+    for (int c = 0; c < C; c += 4) {
+      const float4 a = *reinterpret_cast<const float4*>(t00 + c), b = *reinterpret_cast<const float4*>(t10 + c);
+      const float4 d = *reinterpret_cast<const float4*>(t01 + c), e = *reinterpret_cast<const float4*>(t11 + c);
+      float4 r;
+      r.x = (w00 * a.x + w10 * b.x) + (w01 * d.x + w11 * e.x);
+      r.y = (w00 * a.y + w10 * b.y) + (w01 * d.y + w11 * e.y);
+      r.z = (w00 * a.z + w10 * b.z) + (w01 * d.z + w11 * e.z);
+      r.w = (w00 * a.w + w10 * b.w) + (w01 * d.w + w11 * e.w);
+      *reinterpret_cast<float4*>(o + c) = r;
+    }
+  } else {
+    for (int c = 0; c < C; ++c) o[c] = (w00 * t00[c] + w10 * t10[c]) + (w01 * t01[c] + w11 * t11[c]);
+  }
 }
 
 // --------------------------------------------------------------- backward
@@ -177,9 +197,15 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
 int launch_texture(const mer_plan* P, const mer_view* views, const int32_t* tri_id, const float* uv, int ld_uv,
                    const float* tex, int th, int tw, int C, float* out, hipStream_t st) {
   const long long n = P->total_px - P->px_begin;
-  if (n > 0)
-    hipLaunchKernelGGL(k_texture, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views, tri_id, uv,
-                       ld_uv, tex, th, tw, C, out, P->px_begin, P->total_px);
+  const bool v4 = C % 4 == 0 && ((uintptr_t)tex % 16) == 0 && ((uintptr_t)out % 16) == 0;
+  if (n > 0) {
+    if (v4)
+      hipLaunchKernelGGL(k_texture<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+                         tri_id, uv, ld_uv, tex, th, tw, C, out, P->px_begin, P->total_px);
+    else
+      hipLaunchKernelGGL(k_texture<false>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, views, P->n_views,
+                         tri_id, uv, ld_uv, tex, th, tw, C, out, P->px_begin, P->total_px);
+  }
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 

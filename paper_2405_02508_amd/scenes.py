@@ -386,13 +386,15 @@ def image_grad(scene: Scene, seed: int, C: int | None = None) -> np.ndarray:
     return rng.standard_normal(size=(scene.n_px, C), dtype=np.float32)
 
 
-def texture_inputs(scene: Scene, seed: int, size: int = 1024, channels: int = 8):
+def texture_inputs(scene: Scene, seed: int, size: int = 1024, channels: int = 8, texels_per_pixel: float = 1.0):
     """Seeded stand-ins for a neural texture and per-vertex uv coordinates
     (the paper samples an 8-channel 1024 x 1024 neural texture at
-    interpolated uv).  uv f32 [rows of scene.attr, 2]: each attribute row
-    takes its vertex's screen position in the first view that uses the row,
-    divided by that view's size (a projected texture, smooth on the mesh,
-    partly outside [0, 1]); texture f32 [size, size, channels], N(0, 1)."""
+    interpolated uv, rendering 800 x 800 images: about one texel per
+    pixel).  uv f32 [rows of scene.attr, 2]: each attribute row takes its
+    vertex's screen position in the first view that uses the row, times
+    texels_per_pixel / size (a projected texture, smooth on the mesh;
+    coordinates outside [0, 1] clamp to the edge); texture f32
+    [size, size, channels], N(0, 1)."""
     rng = np.random.default_rng(2000 + seed)
     uv = np.zeros((scene.attr.shape[0], 2), np.float32)
     done = np.zeros(scene.attr.shape[0], bool)
@@ -403,7 +405,7 @@ def texture_inputs(scene: Scene, seed: int, size: int = 1024, channels: int = 8)
         if not todo.any():
             continue
         xy = scene.v[vw["v_off"]: vw["v_off"] + vw["n_v"], :2].astype(np.float64)
-        uv[rows[todo]] = (xy[todo] / np.array([vw["W"], vw["H"]], np.float64)).astype(np.float32)
+        uv[rows[todo]] = (xy[todo] * (texels_per_pixel / size)).astype(np.float32)
         done[rows] = True
     tex = rng.standard_normal((size, size, channels), dtype=np.float32)
     return uv, tex

@@ -77,16 +77,18 @@ def run_sampler(s, tid, uvp, tex, g, with_tid=True, uv_cols=2):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
-@pytest.mark.parametrize("size,C", [(1024, 8), (16, 3)])
-def test_sampler_matches_oracle(k, size, C):
-    """The paper's 8-channel 1024^2 neural texture (minified in small views:
-    the tile's texel box overflows LDS, gradients go straight to memory) and
-    a 16^2 texture (every tile sums in LDS)."""
+@pytest.mark.parametrize("size,C,tpp", [(1024, 8, 1.0), (1024, 8, 8.0), (16, 3, 1.0), (64, 5, 0.25)])
+def test_sampler_matches_oracle(k, size, C, tpp):
+    """The paper's 8-channel 1024^2 neural texture at one texel per pixel
+    (tiles sum their texture gradient in LDS) and minified eight times (a
+    tile's texel box overflows LDS: gradients go straight to memory); a 16^2
+    texture mostly clamped at its edges; a magnified 64^2 texture with 5
+    channels (no vector path)."""
     s = small(k)
-    uv_attr, tex = scenes.texture_inputs(s, k, size=size, channels=C)
+    uv_attr, tex = scenes.texture_inputs(s, k, size=size, channels=C, texels_per_pixel=tpp)
     tid, uvp = oracle_uv(s, uv_attr)
     g = np.random.default_rng(30 + k).standard_normal((s.n_px, C), dtype=np.float32)
-    say(f"[tex] config {k} (small): {s.n_px} px, texture {size}^2 x {C}")
+    say(f"[tex] config {k} (small): {s.n_px} px, texture {size}^2 x {C}, {tpp} texels per pixel")
     out, g_tex, g_uv = run_sampler(s, tid, uvp, tex, g)
     ref = oracle.texture(tex, uvp, tid)
     ref_gt, ref_gu = oracle.texture_bwd(tex, uvp, g, tid)
@@ -99,7 +101,7 @@ def test_sampler_without_index_image_and_strided_uv():
     """tri_id NULL samples every pixel; uv read from a wider image (ld 5);
     out-of-range and non-finite uv."""
     s = small(2)
-    uv_attr, tex = scenes.texture_inputs(s, 2, size=64, channels=4)
+    uv_attr, tex = scenes.texture_inputs(s, 2, size=64, channels=4, texels_per_pixel=0.5)
     _, uvp = oracle_uv(s, uv_attr)
     rng = np.random.default_rng(3)
     uvp = uvp + rng.uniform(-0.3, 0.3, uvp.shape).astype(np.float32)     # background pixels too, some outside [0, 1]
@@ -126,7 +128,7 @@ def test_deferred_texturing_chain(k):
     well inside the tolerance."""
     import torch
     s = small(k)
-    uv_attr, _ = scenes.texture_inputs(s, 10 + k, size=32, channels=4)
+    uv_attr, _ = scenes.texture_inputs(s, 10 + k, size=32, channels=4, texels_per_pixel=0.25)
     rng = np.random.default_rng(60 + k)
     yy, xx = np.mgrid[0:32, 0:32]
     tex = np.stack([np.sin(2 * np.pi * (rng.integers(1, 5) * xx + rng.integers(-4, 5) * yy) / 32 + rng.uniform(0, 6))
