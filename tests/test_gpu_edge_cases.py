@@ -122,3 +122,76 @@ def test_backward_ignores_invalid_index_values():
     torch.cuda.synchronize()
     assert torch.isfinite(g_v).all() and torch.isfinite(g_a).all()
     assert torch.all(out[::7] == 0)
+
+
+def _jvp_and_texture(s, seed):
+    """Forward-mode tangent and texture sampling/adjoint on the GPU against
+    the oracle for an edge-case scene (index image checked bit-exact)."""
+    import torch
+
+    from paper_2405_02508_amd import mer
+    from tests.gpu_util import rel_l2
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(seed)
+    ctx = mer.Context(s.views, device=dev)
+    v, tri, attr = to_dev(s.v), to_dev(s.tri), to_dev(s.attr)
+    n = s.n_px
+    tid = torch.empty(n, dtype=torch.int32, device=dev)
+    img = torch.empty(n, s.C_out, dtype=torch.float32, device=dev)
+    ctx.rasterize(v, tri, tid, None, None)
+    ctx.interpolate(attr, v, tri, tid, img, bary=None, append_z=s.append_z)
+    dv = rng.standard_normal(s.v.shape).astype(np.float32)
+    da = rng.standard_normal(s.attr.shape).astype(np.float32)
+    dimg = torch.full((n, s.C_out), -7.0, dtype=torch.float32, device=dev)
+    ctx.jvp(v, tri, tid, attr, img, to_dev(dv), dimg, dattr=to_dev(da), append_z=s.append_z)
+    f = oracle.forward(s)
+    assert np.array_equal(tid.cpu().numpy(), f["tri_id"])
+    ref = oracle.jvp(s, f, dv, da)
+    got = dimg.cpu().numpy()
+    if np.abs(ref).max() > 0:
+        assert rel_l2(got, ref) <= 1e-5
+        assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max()
+    else:
+        assert np.all(got == 0)
+    # texture at one texel per pixel, uv from the oracle's interpolation
+    uvp = np.zeros((n, 2), np.float32)
+    uv_attr = rng.uniform(0, 1, size=(s.attr.shape[0], 2)).astype(np.float32)
+    for i in range(s.n_views):
+        vw = s.view(i)
+        sl = slice(vw["px_off"], vw["px_off"] + vw["H"] * vw["W"])
+        vs = s.v[vw["v_off"]: vw["v_off"] + vw["n_v"]]
+        ts = s.tri[vw["t_off"]: vw["t_off"] + vw["n_t"]]
+        uvp[sl] = oracle.interpolate(uv_attr[vw["a_off"]: vw["a_off"] + vw["n_v"]], vs, ts, vw["H"], vw["W"],
+                                     f["tri_id"][sl])
+    tex = rng.standard_normal((7, 9, 3)).astype(np.float32)
+    out = torch.full((n, 3), -7.0, dtype=torch.float32, device=dev)
+    ctx.texture(tid, to_dev(uvp), to_dev(tex), out)
+    g = rng.standard_normal((n, 3)).astype(np.float32)
+    g_tex = torch.zeros(7, 9, 3, dtype=torch.float32, device=dev)
+    g_uv = torch.full((n, 2), -7.0, dtype=torch.float32, device=dev)
+    ctx.texture_bwd(tid, to_dev(uvp), to_dev(tex), to_dev(g), g_tex, g_uv)
+    torch.cuda.synchronize()
+    ref_out = oracle.texture(tex, uvp, f["tri_id"])
+    ref_gt, ref_gu = oracle.texture_bwd(tex, uvp, g, f["tri_id"])
+    assert np.all(np.abs(out.cpu().numpy() - ref_out) <= 1e-5 * np.maximum(1, np.abs(ref_out)))
+    for got_t, want in ((g_tex.cpu().numpy(), ref_gt), (g_uv.cpu().numpy(), ref_gu)):
+        if np.abs(want).max() > 0:
+            assert rel_l2(got_t, want) <= 1e-5
+        else:
+            assert np.all(got_t == 0)
+
+
+def test_forward_mode_and_texture_on_empty_and_extreme_views():
+    """mer_jvp, mer_texture and mer_texture_bwd on empty views and meshes,
+    1x1 / 1xN / Nx1 images and a view of degenerate triangles."""
+    say("[edge] forward mode and texture")
+    rng = np.random.default_rng(9)
+    v, t = _random_tris(rng, 30, 20, 24)
+    vd = np.array([[3, 3, 2], [9, 3, 2], [15, 3, 2], [4, 4, 2], [4, 4, 2], [8, 7, 2]], np.float32)  # collinear, repeated
+    td = np.array([[0, 1, 2], [3, 4, 5]], np.int32)
+    v1, t1 = _random_tris(rng, 10, 1, 37, margin=4.0)
+    v2, t2 = _random_tris(rng, 10, 37, 1, margin=4.0)
+    v3, t3 = _random_tris(rng, 5, 1, 1, margin=2.0)
+    s = _scene([(np.zeros((0, 3)), np.zeros((0, 3)), 9, 13), (v, t, 20, 24), (vd, td, 10, 18),
+                (v1, t1, 1, 37), (v2, t2, 37, 1), (v3, t3, 1, 1)])
+    _jvp_and_texture(s, 3)
