@@ -274,9 +274,10 @@ int mer_backward_l2(const mer_plan *plan, const mer_view *views_dev, const float
  *   MER_SKIP_INTERP, img [total_px, C_e] unless MER_SKIP_EDGE (with dv).
  *   dimg: float [total_px, C_e], written.  1 <= C_e <= 64; C_a + append_z
  *   <= C_e when the interior term is on.  flags: MER_NO_INTERSECT,
- *   MER_SKIP_EDGE, MER_SKIP_INTERP.  One workgroup per 16x16 pixel tile,
- *   one thread per pixel, no atomics: the result is deterministic.  Uses
- *   the workspace's view-tile table (as the backward calls do). */
+ *   MER_SKIP_EDGE, MER_SKIP_INTERP.  One wave per 8x8 pixel tile, one
+ *   thread per pixel, no atomics: the result is deterministic.  Uses the
+ *   workspace's view-tile table (rebuilt for 8x8 tiles; the backward calls
+ *   rebuild it for theirs). */
 int mer_jvp(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
             const int32_t *tri_id, const float *attr, const float *dattr, int C_a, int append_z,
             const float *img, int C_e, const float *dv, int flags, float *dimg, void *ws, void *stream);
