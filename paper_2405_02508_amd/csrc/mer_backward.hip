@@ -212,9 +212,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   for (int i = threadIdx.x; i < kSlots; i += blockDim.x) s_key[i] = -1;
   if (threadIdx.x == 0) s_nocc = 0;
 
-  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, tile));
   const mer_view vw = views[vi];
-  const long long local_tile = (long long)blockIdx.x - btile_base[vi];
+  const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + 15) >> 4;
   const int lane = threadIdx.x & 63;
   const int px = (int)(local_tile % tiles_x) * 16 + (lane & 15);
@@ -451,7 +452,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         }
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
-      if (lane == 0) loss_part[4 * (long long)blockIdx.x + (threadIdx.x >> 6)] = w_l2 * e2;
+      if (lane == 0) loss_part[4 * tile + (threadIdx.x >> 6)] = w_l2 * e2;
     }
   }
 }

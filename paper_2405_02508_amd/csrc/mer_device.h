@@ -287,6 +287,16 @@ __device__ __forceinline__ float plane_slope(const Snap& s, int axis) {
   return n256 / (float)s.D;
 }
 
+// Workgroups are dealt to the chip's 8 XCDs round-robin (workgroup b to XCD
+// b % 8), and each XCD has its own L2.  Neighbouring tiles share data (halo
+// pixels, triangles, vertices), so this maps workgroup b to a tile such that
+// each XCD sweeps one contiguous run of tiles: XCD x takes tiles
+// [x q + min(x, r), ...) with q = n / 8, r = n % 8 (a bijection on [0, n)).
+__device__ __forceinline__ long long xcd_tile(long long b, long long n) {
+  const long long q = n >> 3, r = n & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Largest i in [0, n) with base[i] <= g (base non-decreasing, base[0] <= g).
 template <typename T>
 __device__ __forceinline__ int find_bucket(const T* base, int n, long long g) {

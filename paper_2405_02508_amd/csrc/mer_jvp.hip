@@ -58,10 +58,12 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
                                              const float* __restrict__ img, int C_e, const float* __restrict__ dv,
                                              int flags, float* __restrict__ dimg) {
   __shared__ TileTris<TS, true> T;
-  if ((long long)blockIdx.x >= btile_base[n_views]) return;  // the grid may hold spare workgroups
-  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
+  const long long n_tiles = btile_base[n_views];
+  if ((long long)blockIdx.x >= n_tiles) return;  // the grid may hold spare workgroups
+  const long long tile = xcd_tile(blockIdx.x, n_tiles);
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, tile));
   const mer_view vw = views[vi];
-  const long long local_tile = (long long)blockIdx.x - btile_base[vi];
+  const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + TS - 1) / TS;
   const int x0 = (int)(local_tile % tiles_x) * TS, y0 = (int)(local_tile / tiles_x) * TS;
   tile_tris_build<TS, true>(T, vw, x0, y0, tri_id, tri, v, dv);

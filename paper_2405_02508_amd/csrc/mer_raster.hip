@@ -463,7 +463,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   constexpr int NT = TW * TH;
   constexpr bool kEarlyZ = NT == 64;
   __shared__ TileRec s_tr[NT];
-  const long long g = blockIdx.x;
+  const long long g = xcd_tile(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
   const mer_view vw = views[vi];

@@ -112,9 +112,10 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
                                                      float* __restrict__ g_uv) {
   __shared__ float s_acc[kTexWin];
   __shared__ int s_box[4];  // x min, y min, -x max, -y max
-  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, (long long)blockIdx.x));
+  const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, tile));
   const mer_view vw = views[vi];
-  const long long local_tile = (long long)blockIdx.x - btile_base[vi];
+  const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + 15) >> 4;
   const int px = (int)(local_tile % tiles_x) * 16 + (threadIdx.x & 15);
   const int py = (int)(local_tile / tiles_x) * 16 + (threadIdx.x >> 4);

@@ -127,3 +127,52 @@ def test_graph_replay_matches_eager():
         assert rel_l2(st.g_v.cpu().numpy(), gv0.cpu().numpy().astype(np.float64)) <= 1e-5, f"replay {i}: g_v"
         assert rel_l2(st.g_attr.cpu().numpy(), ga0.cpu().numpy().astype(np.float64)) <= 1e-5
         _ = (torch.randn(1000, device="cuda") * 2).sum().item()   # eager work between replays
+
+
+def test_textured_image_through_edge_grad():
+    """The paper's deferred pipeline with torch autograd: Interpolate (uv)
+    -> Texture -> EdgeGrad -> L = sum g * image; gradients to the texture,
+    the uv attribute and the vertices against the same chain in the oracle
+    (texture adjoint, interpolation adjoint with Omega, and the micro-edge
+    term on the textured image).  A smooth texture, and pixels within 1e-3
+    texel of a texel-centre line get dL/d(image) = 0, as in the sampler's
+    chain test."""
+    import torch
+
+    import oracle
+    from paper_2405_02508_amd.autograd import EdgeGrad, Interpolate, Renderer, Texture
+    s = scenes.make_config(2, small=True)
+    say("[autograd] textured image through EdgeGrad, config 2")
+    uv_attr, _ = scenes.texture_inputs(s, 21, size=32, channels=4, texels_per_pixel=0.25)
+    rng = np.random.default_rng(21)
+    yy, xx = np.mgrid[0:32, 0:32]
+    tex = np.stack([np.sin(2 * np.pi * (rng.integers(1, 5) * xx + rng.integers(-4, 5) * yy) / 32 + rng.uniform(0, 6))
+                    for _ in range(4)], -1).astype(np.float32)
+    r = Renderer(s.views, s.tri, append_z=s.append_z, mask_channel=False)
+    v = to_dev(s.v).requires_grad_(True)
+    ua = to_dev(uv_attr).requires_grad_(True)
+    td = to_dev(tex).requires_grad_(True)
+    tid, depth, bary = r.rasterize(v)
+    uv_img = Interpolate.apply(v, ua, tid, bary, r)          # [px, 2 (+ z)]
+    img = EdgeGrad.apply(Texture.apply(uv_img, td, tid, r), v, tid, r)
+    # oracle chain (one view)
+    vw = s.view(0)
+    H, W = vw["H"], vw["W"]
+    t_o = oracle.rasterize(s.v, s.tri, H, W)
+    assert np.array_equal(tid.cpu().numpy(), t_o)
+    uv_o = oracle.interpolate(uv_attr, s.v, s.tri, H, W, t_o, s.append_z)
+    st = uv_o[:, :2] * 32 - 0.5
+    edge = (np.abs(st - np.round(st)) < 1e-3).any(1)
+    g = rng.standard_normal((s.n_px, 4))
+    g[edge] = 0
+    (img * to_dev(g.astype(np.float32))).sum().backward()
+    img_o = oracle.texture(tex, uv_o, t_o)
+    gt_o, gu_o = oracle.texture_bwd(tex, uv_o, g, t_o)
+    g_uv_full = np.zeros((s.n_px, uv_o.shape[1]))
+    g_uv_full[:, :2] = gu_o
+    ga_o, gv_o = oracle.interpolate_bwd(uv_attr, s.v, s.tri, H, W, t_o, g_uv_full, s.append_z)
+    oracle.edge_grad(s.v, s.tri, H, W, t_o, img_o, g, g_v=gv_o)
+    for got, want, name in ((td.grad, gt_o, "g_tex"), (ua.grad, ga_o, "g_uv_attr"), (v.grad, gv_o, "g_v")):
+        err = rel_l2(got.cpu().numpy(), want)
+        say(f"[autograd] {name}: rel L2 {err:.2e}")
+        assert err <= 1e-5, (name, err)
