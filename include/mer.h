@@ -304,8 +304,10 @@ int mer_texture(const mer_plan *plan, const mer_view *views_dev, const int32_t *
 /* Adjoint of mer_texture for dL/d(out) g_out [total_px, C_t]:
  *   g_tex [tex_h, tex_w, C_t] += the transpose of the sampling (each sampled
  *   pixel adds weight * g_out to its four texels; a workgroup sums its 16x16
- *   pixels' contributions in LDS when the box of texels they touch holds at
- *   most 6144 values, else adds them straight to memory with float atomics);
+ *   pixels' contributions in LDS, in 64-bit fixed point scaled to the
+ *   tile's largest |g_out| (exact sums, rounded once to binary32), when the
+ *   box of texels they touch holds at most 3072 values, else adds them
+ *   straight to memory with float atomics);
  *   g_uv [total_px, 2] (written, every pixel of the views) = sum_c g_out[p,c]
  *   d out[p,c] / d(u, v) inside the texel cell: tex_w times the fy-blend of
  *   the two horizontal texel differences, tex_h times the fx-blend of the two

@@ -101,8 +101,18 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
 // pixel.  The texture gradient is summed in LDS over the box of texels the
 // tile touches when that box holds at most kTexWin values (then one global
 // atomic per touched texel channel), else added straight to memory.
-constexpr int kTexWin = 6144;
+//
+// The LDS sums are 64-bit fixed point: LDS float atomics cost about one
+// cycle per active lane on this chip, integer ones a few cycles per
+// instruction.  With M the tile's largest |dL/d(out)| (every contribution
+// w g has |w g| <= M, and a texel takes at most 4 x 256 of them) and
+// M < 2^e, contributions are scaled by 2^(52 - e) and rounded to integers:
+// the sums stay below 2^62, each contribution is rounded by at most
+// 2^(e - 53) <= 2^-52 M, and the sum is exact and independent of order.  A
+// tile with a non-finite dL/d(out) adds straight to memory instead.
+constexpr int kTexWin = 3072;
 
+template <bool V4>
 __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict__ views, int n_views,
                                                      const long long* __restrict__ btile_base,
                                                      const int32_t* __restrict__ tri_id,
@@ -110,8 +120,8 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
                                                      const float* __restrict__ tex, int th, int tw, int C,
                                                      const float* __restrict__ g_out, float* __restrict__ g_tex,
                                                      float* __restrict__ g_uv) {
-  __shared__ float s_acc[kTexWin];
-  __shared__ int s_box[4];  // x min, y min, -x max, -y max
+  __shared__ unsigned long long s_acc[kTexWin];
+  __shared__ int s_box[6];  // x min, y min, -x max, -y max, bits of max |g|, any non-finite g
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(btile_base, n_views, tile));
   const mer_view vw = views[vi];
@@ -122,6 +132,7 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
   const bool inside = px < vw.W && py < vw.H;
   const long long p = vw.px_off + (long long)py * vw.W + px;
   if (threadIdx.x < 4) s_box[threadIdx.x] = 0x7fffffff;
+  if (threadIdx.x == 4 || threadIdx.x == 5) s_box[threadIdx.x] = 0;
 
   const bool want = inside && (!tri_id || tri_id[p] >= 0);
   const TexCell cell = tex_cell(want, want ? uv[p * ld_uv] : 0.f, want ? uv[p * ld_uv + 1] : 0.f, th, tw);
@@ -131,19 +142,45 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
   const long long r00 = ((long long)cell.y[0] * tw + cell.x[0]) * C, r10 = ((long long)cell.y[0] * tw + cell.x[1]) * C;
   const long long r01 = ((long long)cell.y[1] * tw + cell.x[0]) * C, r11 = ((long long)cell.y[1] * tw + cell.x[1]) * C;
 
+  float gmax = 0.f;
+  bool gbad = false;
   if (g_uv && inside) {
     float du = 0.f, dv = 0.f;
     if (cell.ok) {
-      for (int c = 0; c < C; ++c) {
-        const float t00 = tex[r00 + c], t10 = tex[r10 + c], t01 = tex[r01 + c], t11 = tex[r11 + c];
-        du += g[c] * ((1.0f - cell.fy) * (t10 - t00) + cell.fy * (t11 - t01));
-        dv += g[c] * ((1.0f - cell.fx) * (t01 - t00) + cell.fx * (t11 - t10));
+      if constexpr (V4) {
+        for (int c = 0; c < C; c += 4) {
+          const float4 gg = *reinterpret_cast<const float4*>(g + c);
+          const float4 a = *reinterpret_cast<const float4*>(tex + r00 + c);
+          const float4 b = *reinterpret_cast<const float4*>(tex + r10 + c);
+          const float4 d = *reinterpret_cast<const float4*>(tex + r01 + c);
+          const float4 f = *reinterpret_cast<const float4*>(tex + r11 + c);
+          const float gs[4] = {gg.x, gg.y, gg.z, gg.w};
+          const float t00[4] = {a.x, a.y, a.z, a.w}, t10[4] = {b.x, b.y, b.z, b.w};
+          const float t01[4] = {d.x, d.y, d.z, d.w}, t11[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            du += gs[k] * ((1.0f - cell.fy) * (t10[k] - t00[k]) + cell.fy * (t11[k] - t01[k]));
+            dv += gs[k] * ((1.0f - cell.fx) * (t01[k] - t00[k]) + cell.fx * (t11[k] - t10[k]));
+          }
+        }
+      } else {
+        for (int c = 0; c < C; ++c) {
+          const float t00 = tex[r00 + c], t10 = tex[r10 + c], t01 = tex[r01 + c], t11 = tex[r11 + c];
+          du += g[c] * ((1.0f - cell.fy) * (t10 - t00) + cell.fy * (t11 - t01));
+          dv += g[c] * ((1.0f - cell.fx) * (t01 - t00) + cell.fx * (t11 - t10));
+        }
       }
     }
     g_uv[2 * p] = du * (float)tw;
     g_uv[2 * p + 1] = dv * (float)th;
   }
   if (!g_tex) return;  // uniform: every thread leaves before the barriers
+  if (cell.ok)
+    for (int c = 0; c < C; ++c) {
+      const float a = fabsf(g[c]);
+      gbad |= !(a <= 3.40282347e38f);  // inf or NaN
+      gmax = fmaxf(gmax, a);
+    }
 
   __syncthreads();  // s_box initialised
   if (cell.ok) {
@@ -151,14 +188,17 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
     atomicMin(&s_box[1], cell.y[0]);
     atomicMin(&s_box[2], -cell.x[1]);
     atomicMin(&s_box[3], -cell.y[1]);
+    atomicMax(&s_box[4], __float_as_int(gmax));  // gmax >= 0: its bits order like its value
+    if (gbad) atomicOr(&s_box[5], 1);
   }
   __syncthreads();
   const int bx0 = s_box[0], by0 = s_box[1];
   const bool any = bx0 != 0x7fffffff;
   const long long bw = any ? (long long)(-s_box[2]) - bx0 + 1 : 0, bh = any ? (long long)(-s_box[3]) - by0 + 1 : 0;
   const long long nwin = bw * bh * C;
-  if (!any) return;  // uniform
-  if (nwin > kTexWin) {
+  const float M = __int_as_float(s_box[4]);
+  if (!any || M == 0.f) return;  // nothing to add (uniform)
+  if (nwin > kTexWin || s_box[5]) {
     if (cell.ok)
       for (int c = 0; c < C; ++c) {
         const float gc = g[c];
@@ -170,7 +210,10 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
       }
     return;
   }
-  for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) s_acc[i] = 0.f;
+  int e;
+  frexpf(M, &e);  // M < 2^e
+  const int sh = 52 - e;
+  for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) s_acc[i] = 0ull;
   __syncthreads();
   if (cell.ok) {
     const int l00 = (int)(((cell.y[0] - by0) * bw + (cell.x[0] - bx0)) * C);
@@ -179,19 +222,21 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
     const int l11 = (int)(((cell.y[1] - by0) * bw + (cell.x[1] - bx0)) * C);
     for (int c = 0; c < C; ++c) {
       const float gc = g[c];
-      atomicAdd(&s_acc[l00 + c], w00 * gc);
-      atomicAdd(&s_acc[l10 + c], w10 * gc);
-      atomicAdd(&s_acc[l01 + c], w01 * gc);
-      atomicAdd(&s_acc[l11 + c], w11 * gc);
+      if (gc == 0.f) continue;
+      // |w g 2^sh| < 2^52: exact in binary64, rounded to the nearest integer
+      atomicAdd(&s_acc[l00 + c], (unsigned long long)(long long)rint(ldexp((double)(w00 * gc), sh)));
+      atomicAdd(&s_acc[l10 + c], (unsigned long long)(long long)rint(ldexp((double)(w10 * gc), sh)));
+      atomicAdd(&s_acc[l01 + c], (unsigned long long)(long long)rint(ldexp((double)(w01 * gc), sh)));
+      atomicAdd(&s_acc[l11 + c], (unsigned long long)(long long)rint(ldexp((double)(w11 * gc), sh)));
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) {
-    const float x = s_acc[i];
-    if (x == 0.f) continue;
+    const long long q = (long long)s_acc[i];
+    if (q == 0) continue;
     const int c = i % C, cell_i = i / C;
     const long long ty = by0 + cell_i / bw, tx = bx0 + cell_i % bw;
-    atomicAdd(g_tex + (ty * tw + tx) * C + c, x);
+    atomicAdd(g_tex + (ty * tw + tx) * C + c, (float)ldexp((double)q, -sh));
   }
 }
 
@@ -216,9 +261,15 @@ int launch_texture_bwd(const mer_plan* P, const mer_view* views, const int32_t* 
   long long* tab = (long long*)((char*)ws + P->off_bviewtab);
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, 4, 4, tab, tab + (P->n_views + 1),
                      (long long*)nullptr);
-  if (P->total_btiles > 0)
-    hipLaunchKernelGGL(k_texture_bwd, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
-                       tab + (P->n_views + 1), tri_id, uv, ld_uv, tex, th, tw, C, g_out, g_tex, g_uv);
+  const bool v4 = C % 4 == 0 && ((uintptr_t)tex % 16) == 0 && ((uintptr_t)g_out % 16) == 0;
+  if (P->total_btiles > 0) {
+    if (v4)
+      hipLaunchKernelGGL(k_texture_bwd<true>, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
+                         tab + (P->n_views + 1), tri_id, uv, ld_uv, tex, th, tw, C, g_out, g_tex, g_uv);
+    else
+      hipLaunchKernelGGL(k_texture_bwd<false>, dim3((unsigned)P->total_btiles), dim3(256), 0, st, views, P->n_views,
+                         tab + (P->n_views + 1), tri_id, uv, ld_uv, tex, th, tw, C, g_out, g_tex, g_uv);
+  }
   return hipGetLastError() == hipSuccess ? MER_OK : MER_ELAUNCH;
 }
 
