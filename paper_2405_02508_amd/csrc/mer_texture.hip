@@ -182,14 +182,28 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
       gmax = fmaxf(gmax, a);
     }
 
+  // per-wave reductions (every lane takes part), then one atomic per wave
+  const int big = 0x7fffffff;
+  int r0 = cell.ok ? cell.x[0] : big, r1 = cell.ok ? cell.y[0] : big;
+  int r2 = cell.ok ? -cell.x[1] : big, r3 = cell.ok ? -cell.y[1] : big;
+  int r4 = __float_as_int(gmax), r5 = gbad ? 1 : 0;  // gmax >= 0: its bits order like its value
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    r0 = min(r0, __shfl_xor(r0, o, 64));
+    r1 = min(r1, __shfl_xor(r1, o, 64));
+    r2 = min(r2, __shfl_xor(r2, o, 64));
+    r3 = min(r3, __shfl_xor(r3, o, 64));
+    r4 = max(r4, __shfl_xor(r4, o, 64));
+    r5 = r5 | __shfl_xor(r5, o, 64);
+  }
   __syncthreads();  // s_box initialised
-  if (cell.ok) {
-    atomicMin(&s_box[0], cell.x[0]);
-    atomicMin(&s_box[1], cell.y[0]);
-    atomicMin(&s_box[2], -cell.x[1]);
-    atomicMin(&s_box[3], -cell.y[1]);
-    atomicMax(&s_box[4], __float_as_int(gmax));  // gmax >= 0: its bits order like its value
-    if (gbad) atomicOr(&s_box[5], 1);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&s_box[0], r0);
+    atomicMin(&s_box[1], r1);
+    atomicMin(&s_box[2], r2);
+    atomicMin(&s_box[3], r3);
+    atomicMax(&s_box[4], r4);
+    if (r5) atomicOr(&s_box[5], 1);
   }
   __syncthreads();
   const int bx0 = s_box[0], by0 = s_box[1];
