@@ -8,6 +8,10 @@ gradient 2 (I - T) is formed inside the backward kernel.
 Batched = all views of the workload in one captured HIP graph; per-view =
 the same calls issued view by view without a graph.
 
+Beside the step, on the same pixels and outside its timed region, it times
+the forward-mode image tangent (field ``jvp``) and deferred texturing with an
+8-channel 1024^2 texture, forward and adjoint (field ``texture``).
+
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build measures
 one GPU.
 """
