@@ -12,8 +12,9 @@ Beside the step, on the same pixels and outside its timed region, it times
 the forward-mode image tangent (field ``jvp``) and deferred texturing with an
 8-channel 1024^2 texture, forward and adjoint (field ``texture``).
 
-Prints ONE JSON line.  ``--gpus`` above 1 is refused: this build measures
-one GPU.
+Prints ONE JSON line.  ``--gpus`` above 1 is refused: the benchmark
+measures one GPU (views shard across GPUs with one gradient all-reduce, which
+is not part of it).
 """
 from __future__ import annotations
 
@@ -314,7 +315,7 @@ def main():
                          "byte counters, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
