@@ -8,9 +8,10 @@ gradient 2 (I - T) is formed inside the backward kernel.
 Batched = all views of the workload in one captured HIP graph; per-view =
 the same calls issued view by view without a graph.
 
-Beside the step, on the same pixels and outside its timed region, it times
-the forward-mode image tangent (field ``jvp``) and deferred texturing with an
-8-channel 1024^2 texture, forward and adjoint (field ``texture``).
+With ``--extras`` it also times, on the same pixels and outside the step's
+timed region, the forward-mode image tangent (field ``jvp``) and deferred
+texturing with an 8-channel 1024^2 texture, forward and adjoint (field
+``texture``).
 
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: the benchmark
 measures one GPU (views shard across GPUs with one gradient all-reduce, which
@@ -310,6 +311,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the forward-mode image tangent and the texture sampler on the step's pixels")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to scale HBM "
                          "byte counters, and exit")
@@ -383,10 +386,31 @@ def main():
     log(f"[bench] batched {'graph' if graph else 'eager'}: {ms:.3f} ms/step")
     kt = kernel_times(st, max(3, min(args.steps, 10)), stream)
     log(f"[bench] per-call ms: {kt}")
-    jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
-    log(f"[bench] forward-mode image tangent: {jvp_ms:.3f} ms per call")
-    tex_ms = texture_time(st, max(3, min(args.steps, 10)), stream)
-    log(f"[bench] texture sampler 1024^2 x 8: {tex_ms}")
+    extras = {}
+    if args.extras:
+        jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
+        log(f"[bench] forward-mode image tangent: {jvp_ms:.3f} ms per call")
+        tex_ms = texture_time(st, max(3, min(args.steps, 10)), stream)
+        log(f"[bench] texture sampler 1024^2 x 8: {tex_ms}")
+        jb, tb, tbb = algorithmic_bytes(s, "jvp"), algorithmic_bytes(s, "texture"), algorithmic_bytes(s, "texture_bwd")
+        # forward-mode image tangent of the same image (Sec. 5, forward
+        # gradients), and deferred texturing of the same pixels with an
+        # 8-channel 1024^2 texture: each its own call, outside the step
+        extras = {
+            "jvp": {"kernel": "k_jvp", "ms_per_call": round(jvp_ms, 4), "value": round(s.n_px / jvp_ms / 1e3, 2),
+                    "unit": "Mpx/s",
+                    "roofline": {"bound": "hbm", "achieved": round(jb / (jvp_ms * 1e-3) / 1e9, 1), "peak": PEAK_HBM_GBS,
+                                 "unit": "GB/s", "frac": round(jb / (jvp_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                                 "algorithmic_bytes": jb}},
+            "texture": {"kernels": ["k_texture", "k_texture_bwd"], "texture": [1024, 1024, 8],
+                        "ms_forward": round(tex_ms["forward"], 4), "ms_backward": round(tex_ms["backward"], 4),
+                        "roofline_forward": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                             "achieved": round(tb / (tex_ms["forward"] * 1e-3) / 1e9, 1),
+                                             "algorithmic_bytes": tb},
+                        "roofline_backward": {"bound": "alu", "peak": None, "unit": "GB/s",
+                                              "achieved": round(tbb / (tex_ms["backward"] * 1e-3) / 1e9, 1),
+                                              "algorithmic_bytes": tbb}},
+        }
     status = st.ctxs[0].status()
     log(f"[bench] status {status}")
 
@@ -433,24 +457,7 @@ def main():
                      "traffic": stored_traffic(args.workload, "k_backward"),
                      "algorithmic_bytes": ab, "avg_launch_ms": round(kt[dom], 4), "src_hash": source_hash()},
         "cpu_baseline": None,
-        # forward-mode image tangent of the same image (Sec. 5, forward
-        # gradients): its own call, outside the step
-        "jvp": {"kernel": "k_jvp", "ms_per_call": round(jvp_ms, 4), "value": round(s.n_px / jvp_ms / 1e3, 2),
-                "unit": "Mpx/s",
-                "roofline": {"bound": "hbm", "achieved": round(algorithmic_bytes(s, "jvp") / (jvp_ms * 1e-3) / 1e9, 1),
-                             "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                             "frac": round(algorithmic_bytes(s, "jvp") / (jvp_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-                             "algorithmic_bytes": algorithmic_bytes(s, "jvp")}},
-        # deferred texturing of the same pixels: an 8-channel 1024^2 texture
-        # sampled at interpolated uv, and its adjoint (texture and uv)
-        "texture": {"kernels": ["k_texture", "k_texture_bwd"], "texture": [1024, 1024, 8],
-                    "ms_forward": round(tex_ms["forward"], 4), "ms_backward": round(tex_ms["backward"], 4),
-                    "roofline_forward": {"bound": "hbm", "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                         "achieved": round(algorithmic_bytes(s, "texture") / (tex_ms["forward"] * 1e-3) / 1e9, 1),
-                                         "algorithmic_bytes": algorithmic_bytes(s, "texture")},
-                    "roofline_backward": {"bound": "atomics", "peak": None, "unit": "GB/s",
-                                          "achieved": round(algorithmic_bytes(s, "texture_bwd") / (tex_ms["backward"] * 1e-3) / 1e9, 1),
-                                          "algorithmic_bytes": algorithmic_bytes(s, "texture_bwd")}},
+        **extras,
     }
     if not args.no_cpu:
         del st
