@@ -1,6 +1,7 @@
 """The C-ABI library loads and exports what include/mer.h declares; the
 host-only plan call validates its inputs.  No GPU needed."""
 import ctypes
+import functools
 import os
 import re
 import subprocess
@@ -80,6 +81,66 @@ def test_plan_totals_and_layout(L):
     assert P2.bin_cap == 5 and P2.total_tiles == 2 * 3 + 1
     # bin offsets are 32-bit and saturate at INT_MAX, so the pool stays below it
     assert mer.plan_init(V, (8, 8), bin_cap=1 << 40).bin_cap == 2**31 - 2
+
+
+def _regions(P):
+    """(name, offset, bytes the kernels index) for every workspace region:
+    the view tables, the set-up records and boxes, the tile counters, offsets
+    and scan partials, the bin pool, the status words, the 64-bit key image,
+    the 16x16-tile view table, the vertex bases, the per-wave loss partials,
+    and the per-workgroup large-triangle lists with their lengths, offsets,
+    scan partials and flat copy."""
+    nv, T, ng = P.n_views, P.total_tiles, P.n_bingroups
+    return [
+        ("viewtab", P.off_viewtab, 2 * (nv + 1) * 8),
+        ("rec", P.off_rec, P.total_tris * 64),
+        ("bbox", P.off_bbox, P.total_tris * 8),
+        ("count", P.off_count, T * 4),
+        ("offs", P.off_offs, (T + 1) * 4),
+        ("part", P.off_part, -(-T // 1024) * 8),
+        ("bins", P.off_bins, P.bin_cap * 4),
+        ("status", P.off_status, 8 * 8),
+        ("key", P.off_key, (P.total_px - P.px_begin) * 8),
+        ("bviewtab", P.off_bviewtab, 2 * (nv + 1) * 8),
+        ("vbase", P.off_vbase, (nv + 1) * 8),
+        ("bloss", P.off_bloss, 4 * P.total_btiles * 4),
+        ("big", P.off_big, ng * 256 * 4),
+        ("bign", P.off_bign, (2 * ng + 1) * 4),
+        ("bigpart", P.off_bigpart, -(-ng // 1024) * 8),
+        ("bigflat", P.off_bigflat, P.total_tris * 4),
+    ]
+
+
+@functools.lru_cache(maxsize=None)
+def _full_views(k):
+    from paper_2405_02508_amd import scenes
+    return scenes.make_config(k).views
+
+
+def _tiles(V, tw, th):
+    return int(sum(-(-int(w) // tw) * -(-int(h) // th) for h, w in zip(V[:, 6], V[:, 7])))
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [(8, 8), (16, 16), (32, 8), (16, 8)])
+def test_plan_regions_hold_what_the_kernels_index(L, k, tile):
+    """Every workspace region is 256-byte aligned, lies inside ws_bytes and
+    is at least as large as the kernels index it, with no two regions
+    overlapping, for the full-size view tables; the counts the launches size
+    their grids from agree with the view table (the forward-mode sweep covers
+    its 8x8 tiles with four workgroups per 16x16 tile)."""
+    V = _full_views(k)
+    P = mer.plan_init(V, tile)
+    assert P.total_tiles == _tiles(V, *tile)
+    assert P.total_btiles == _tiles(V, 16, 16)
+    assert _tiles(V, 8, 8) <= 4 * P.total_btiles
+    assert P.n_part == -(-P.total_tiles // 1024)
+    assert P.n_bingroups == -(-P.total_tris // 256)
+    assert P.total_px - P.px_begin == int((V[:, 6] * V[:, 7]).sum())
+    regs = sorted(_regions(P), key=lambda r: r[1])
+    for (name, off, size), nxt in zip(regs, regs[1:] + [("end", P.ws_bytes, 0)]):
+        assert off % 256 == 0, name
+        assert off + size <= nxt[1], f"{name} [{off}, {off + size}) runs into {nxt[0]} at {nxt[1]}"
 
 
 @pytest.mark.parametrize("bad", [
