@@ -13,6 +13,12 @@ timed region, the forward-mode image tangent (field ``jvp``) and deferred
 texturing with an 8-channel 1024^2 texture, forward and adjoint (field
 ``texture``).
 
+The roofline object is for the backward sweep: algorithmic bytes over its
+measured launch time against HBM peak, the HBM bytes from stored rocprofv3
+counters (``traffic``), and the time its VALU instructions take at the
+chip's issue rate over the launch time (``valu_issue``); the stored figures
+are reported only while the kernel's sources hash to what they were taken on.
+
 Prints ONE JSON line.  ``--gpus`` above 1 is refused: the benchmark
 measures one GPU (views shard across GPUs with one gradient all-reduce, which
 is not part of it).
@@ -284,6 +290,27 @@ def stored_traffic(workload, kernel):
     return int(1024 * (e["fetch_kib"] * t["fetch_scale"] + e["write_kib"] * t["write_scale"]))
 
 
+VALU_ISSUE_PER_S = 256 * 2.4e9  # wave64 VALU instructions per second: one per CU per cycle
+
+
+def stored_valu_issue(workload, kernel, launch_ms):
+    """Time the kernel's VALU instructions take at the chip's issue rate,
+    and that time over the measured launch, from a stored SQ_INSTS_VALU
+    count (rocprofv3 --pmc); None when absent or taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("src_hash") != source_hash():
+        return None
+    n = t.get("workloads", {}).get(str(workload), {}).get(kernel, {}).get("valu_instr")
+    if not n:
+        return None
+    ms = n / VALU_ISSUE_PER_S * 1e3
+    return {"valu_instr": n, "issue_ms": round(ms, 4), "frac": round(ms / launch_ms, 4)}
+
+
 def cpu_baseline(scene, budget_s=15.0):
     """The CPU oracle as it stands (single thread) on a bounded sample of the
     workload: whole views, forward + backward, until the time budget is used."""
@@ -455,6 +482,7 @@ def main():
         "roofline": {"kernel": "k_backward", "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": stored_traffic(args.workload, "k_backward"),
+                     "valu_issue": stored_valu_issue(args.workload, "k_backward", kt[dom]),
                      "algorithmic_bytes": ab, "avg_launch_ms": round(kt[dom], 4), "src_hash": source_hash()},
         "cpu_baseline": None,
         **extras,
