@@ -217,3 +217,13 @@ def test_calls_reject_null_arguments_before_any_launch(L):
     assert L.mer_texture_bwd(p, fake, None, fake, 2, fake, 4, 4, 3, fake, fake, fake, None, None) == -2
     assert L.mer_status(p, None, None, (ctypes.c_int64 * 4)()) == -2
     assert L.mer_plan_init(None, 1, None, p) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """No fallback: without the built library every call path raises."""
+    monkeypatch.setattr(mer, "LIB_PATH", str(tmp_path / "absent" / "libmer.so"))
+    monkeypatch.setattr(mer, "_lib", None)
+    with pytest.raises(mer.MerError, match="missing"):
+        mer.lib()
+    with pytest.raises(mer.MerError, match="missing"):
+        mer.plan_init(_views([[0, 0, 0, 0, 3, 1, 8, 8]]))
