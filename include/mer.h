@@ -47,6 +47,8 @@ extern "C" {
 #define MER_EWORKSPACE (-2) /* workspace pointer null / plan inconsistent    */
 #define MER_ELAUNCH (-3)    /* a kernel launch failed (hipGetLastError)      */
 #define MER_ETUNING (-4)    /* unsupported tile shape                        */
+#define MER_EINTERNAL (-5)  /* mer_status: an integrity check of the last
+                               mer_rasterize failed (a library defect)      */
 
 /* edge-gradient flags */
 #define MER_NO_INTERSECT 1  /* ablation: intersection pairs scatter nothing   */
@@ -323,8 +325,12 @@ int mer_texture_bwd(const mer_plan *plan, const mer_view *views_dev, const int32
  * mer_rasterize: out[0] tiles whose triangle list overflowed the bin pool
  * (they were rasterized by the slower fallback, results unchanged),
  * out[1] culled triangles, out[2] triangle-tile entries needed, out[3]
- * bin pool capacity. */
-int mer_status(const mer_plan *plan, const void *ws, void *stream, int64_t out[4]);
+ * bin pool capacity, and two integrity counts that are 0 unless the library
+ * is defective: out[4] bin entries that did not name a triangle of their
+ * tile's view (skipped, not read), out[5] tiles whose counter the binning
+ * passes did not take back to 0 (their list has an unwritten position).
+ * Returns MER_EINTERNAL, with out[] filled, when out[4] or out[5] is not 0. */
+int mer_status(const mer_plan *plan, const void *ws, void *stream, int64_t out[6]);
 
 const char *mer_strerror(int code);
 int mer_version(void);

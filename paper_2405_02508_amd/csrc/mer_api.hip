@@ -29,6 +29,7 @@ const char* mer_strerror(int code) {
     case MER_EWORKSPACE: return "workspace missing or inconsistent with the plan";
     case MER_ELAUNCH: return "kernel launch failed";
     case MER_ETUNING: return "unsupported tile shape";
+    case MER_EINTERNAL: return "binning integrity check failed (library defect)";
     default: return "unknown error";
   }
 }
@@ -244,7 +245,7 @@ int mer_texture_bwd(const mer_plan* P, const mer_view* views_dev, const int32_t*
                                  (hipStream_t)stream);
 }
 
-int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) {
+int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[6]) {
   if (!plan_ok(P) || !out) return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
   long long st[8];
@@ -256,7 +257,9 @@ int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[4]) 
   out[1] = st[1];
   out[2] = st[2];
   out[3] = P->bin_cap;
-  return MER_OK;
+  out[4] = st[5];
+  out[5] = st[6];
+  return (st[5] != 0 || st[6] != 0) ? MER_EINTERNAL : MER_OK;
 }
 
 }  // extern "C"

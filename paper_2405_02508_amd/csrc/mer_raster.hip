@@ -118,9 +118,11 @@ __device__ __forceinline__ void wave_each_tile(const Rec& R, const BBox& bb, int
 }
 
 // Workgroup table of tile counters: the count and fill passes add into LDS
-// and touch each tile's global counter once per workgroup.  The table stops
-// taking new tiles at 3/4 occupancy (a workgroup of large triangles can meet
-// thousands of tiles); tiles left out use their global counter directly.
+// and touch each tile's global counter once per workgroup (a workgroup of
+// large triangles can meet thousands of tiles; tiles the table does not take
+// use their global counter directly).  A key lives in a window of kBinProbe
+// slots from its hash; slots go from empty to a key once and never change
+// again.
 constexpr int kBinLog2 = 10;    // table of 2^kBinLog2 tile slots
 constexpr int kBinSlots = 1 << kBinLog2;
 constexpr int kBinFull = kBinSlots * 3 / 4;
@@ -134,9 +136,21 @@ __device__ __forceinline__ void clear_tile_table(int* s_tkey, int* s_tcnt, int* 
   if (threadIdx.x == 0) *s_nocc = 0;
 }
 
-// Slot of tile `key`, inserting it if INSERT and the table has room; -1 if
-// absent.  After the inserting phase (and a barrier) lookups are stable.
-template <bool INSERT>
+// Slot of tile `key`, inserting it if INSERT; -1 if absent.
+//
+// Without CUTOFF a key is refused only when every slot of its window holds
+// another key.  That cannot change later, and a key once in the table stays
+// there, so an inserting lookup and a later frozen lookup (INSERT = false,
+// after a barrier) of the same key always agree.  The fill pass depends on
+// this: its two passes must make the same decision for every entry, or an
+// entry counted outside the workgroup's range would be written inside it.
+//
+// CUTOFF also refuses a new key once 3/4 of the slots are taken, which keeps
+// probe windows short; the decision then depends on timing (a lane can be
+// refused at an empty slot that another lane fills with the same key a
+// moment later), so it is only for the count pass, where a refused entry is
+// simply counted in global memory instead.
+template <bool INSERT, bool CUTOFF>
 __device__ __forceinline__ int tile_slot(int* s_tkey, int* s_nocc, int key) {
   const unsigned h = ((unsigned)key * 2654435761u) >> (32 - kBinLog2);
 #pragma unroll 1
@@ -145,10 +159,10 @@ __device__ __forceinline__ int tile_slot(int* s_tkey, int* s_nocc, int key) {
     const int cur = s_tkey[sl];
     if (cur == key) return sl;
     if (cur == -1) {
-      if (!INSERT || *s_nocc >= kBinFull) return -1;
+      if (!INSERT || (CUTOFF && *s_nocc >= kBinFull)) return -1;
       const int old = atomicCAS(&s_tkey[sl], -1, key);
       if (old == -1) {
-        atomicAdd(s_nocc, 1);
+        if (CUTOFF) atomicAdd(s_nocc, 1);
         return sl;
       }
       if (old == key) return sl;
@@ -221,7 +235,7 @@ __global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict_
           s_big[atomicAdd(&s_nbig, 1)] = (int)g;  // counted by k_bin_big
         } else {
           for_each_tile(R, bb, vw.W, tile_base[vi], tw_log2, th_log2, [&](int gt) {
-            const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
+            const int sl = tile_slot<true, true>(s_tkey, &s_nocc, gt);
             if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
             else atomicAdd(count + gt, 1);
           });
@@ -332,7 +346,9 @@ __global__ void __launch_bounds__(256) k_scan_final(const int* __restrict__ coun
 // Each workgroup counts its entries per tile in LDS, reserves one contiguous
 // range per tabled tile with a single global atomic, then writes its entries:
 // into that range, or for a tile the table did not take, at a position taken
-// from the tile's global counter.
+// from the tile's global counter.  Both passes must agree on which entries
+// are tabled (tile_slot without CUTOFF); then every tile's counter ends at 0
+// and each position of its list is written once.
 __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__ views, int n_views,
                                               const long long* __restrict__ tri_base,
                                               const long long* __restrict__ tile_base, long long total_tris,
@@ -356,7 +372,7 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
     base = tile_base[vi];
     R = rec[g];
     for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
-      const int sl = tile_slot<true>(s_tkey, &s_nocc, gt);
+      const int sl = tile_slot<true, false>(s_tkey, &s_nocc, gt);
       if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
     });
   }
@@ -374,7 +390,7 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
   // workgroup's range, any other tile its own global counter
   if (live) {
     for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
-      const int sl = tile_slot<false>(s_tkey, &s_nocc, gt);
+      const int sl = tile_slot<false, false>(s_tkey, &s_nocc, gt);
       const long long pos = sl >= 0 ? (long long)s_toff[sl] + atomicAdd(&s_tcnt[sl], 1)
                                     : (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
       if (pos < bin_cap) bins[pos] = (int)g;
@@ -454,6 +470,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    const long long* __restrict__ tile_base,
                                                    const Rec* __restrict__ rec, const BBox* __restrict__ bbox,
                                                    const int* __restrict__ offs, const int* __restrict__ bins,
+                                                   const int* __restrict__ count,
                                                    long long bin_cap, const unsigned long long* __restrict__ key,
                                                    long long px_begin, const float* __restrict__ v,
                                                    const int32_t* __restrict__ tri, int32_t* __restrict__ tri_id,
@@ -461,7 +478,6 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    long long* __restrict__ status, const float* __restrict__ attr,
                                                    int C_a, int append_z, float* __restrict__ out) {
   constexpr int NT = TW * TH;
-  constexpr bool kEarlyZ = NT == 64;
   __shared__ TileRec s_tr[NT];
   const long long g = xcd_tile(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
@@ -474,13 +490,17 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const int px = x0 + lx, py = y0 + ly;
   const int dxs = lx * 256, dys = ly * 256;
   const bool inside = px < vw.W && py < vw.H;
-  const long long tb = tri_base[vi];
+  const long long tb = tri_base[vi], tb_end = tri_base[vi + 1];
 
   const long long start = offs[g], end = offs[g + 1];
   const bool overflow = end > bin_cap;
   // overflow fallback: scan every record of the view, filtered by bbox
-  const long long n_items = overflow ? (tri_base[vi + 1] - tb) : (end - start);
-  if (overflow && lt == 0) atomicAdd((unsigned long long*)status, 1ull);
+  const long long n_items = overflow ? (tb_end - tb) : (end - start);
+  if (lt == 0) {
+    if (overflow) atomicAdd((unsigned long long*)status, 1ull);
+    // integrity: the fill passes take every tile counter back to 0
+    if (count[g] != 0) atomicAdd((unsigned long long*)status + 6, 1ull);
+  }
 
   const long long p = vw.px_off + (long long)py * vw.W + px;
   // key: the small-triangle pass's result, or NULL when that pass is off
@@ -496,6 +516,12 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
       bool keep = true;
       if (!overflow) {
         r = bins[start + c0 + lt];
+        // integrity: a bin entry names a record of this tile's view; any
+        // other value is counted (mer_status fails on it) and not read
+        if (r < tb || r >= tb_end) {
+          keep = false;
+          atomicAdd((unsigned long long*)status + 5, 1ull);
+        }
       } else {
         r = tb + c0 + lt;
         const BBox bb = bbox[r];
@@ -523,11 +549,10 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         o.fast = (R.tl & 8) && Dabs < 2147483648ll;
         // Early z: the key is a convex combination of the vertices' 1/z up to
         // a few roundings (< 2^-20 relative), so a lane whose surface is
-        // already nearer than every vertex skips the key.  Enabled for
-        // single-wave tiles only: with multi-wave tiles it produced wrong
-        // index images whose cause was not found (the rule itself checks out
-        // in-kernel), so those tiles compute every covered key.
-        o.qb = kEarlyZ ? fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f) : INFINITY;
+        // already strictly nearer than every vertex skips the key (it could
+        // not win, not even the tie on equal 1/z).  The test is per lane, so
+        // it holds for every tile shape.
+        o.qb = fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f);
         o.t = (int)(r - tb);
         o.tneg = 0xFFFFFFFFu - (unsigned)o.t;
       }
@@ -703,11 +728,11 @@ int launch_rasterize(const mer_plan* P, const mer_view* views, const float* v, c
   do {                                                                                                   \
     if (bary)                                                                                            \
       hipLaunchKernelGGL((k_raster<TW, TH, true>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,      \
-                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
+                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, count, P->bin_cap, key, \
                          P->px_begin, v, tri, tri_id, depth, bary, status, attr, C_a, append_z, out);    \
     else                                                                                                 \
       hipLaunchKernelGGL((k_raster<TW, TH, false>), dim3((unsigned)nt), dim3(TW * TH), 0, st, views,     \
-                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, P->bin_cap, key,        \
+                         P->n_views, tri_base, tile_base, rec, bbox, offs, bins, count, P->bin_cap, key, \
                          P->px_begin, v, tri, tri_id, depth, bary, status, attr, C_a, append_z, out);    \
   } while (0)
   if (P->tile_w == 8 && P->tile_h == 8) MER_RASTER(8, 8);

@@ -436,9 +436,15 @@ class Context:
                                      _stream()))
 
     def status(self):
-        out = (ctypes.c_int64 * 4)()
-        _check(lib().mer_status(ctypes.byref(self.plan), _ptr(self.ws), _stream(), out))
-        return dict(overflow_tiles=out[0], culled=out[1], entries=out[2], bin_cap=out[3])
+        """Status of the last rasterize on this workspace (waits for the
+        stream).  Raises MerError if an integrity count is not zero."""
+        out = (ctypes.c_int64 * 6)()
+        rc = lib().mer_status(ctypes.byref(self.plan), _ptr(self.ws), _stream(), out)
+        st = dict(overflow_tiles=out[0], culled=out[1], entries=out[2], bin_cap=out[3], bad_entries=out[4],
+                  unbalanced_tiles=out[5])
+        if rc != 0:
+            raise MerError(f"mer error {rc}: {lib().mer_strerror(rc).decode()} {st}")
+        return st
 
 
 class Cameras:

@@ -409,3 +409,21 @@ def texture_inputs(scene: Scene, seed: int, size: int = 1024, channels: int = 8,
         done[rows] = True
     tex = rng.standard_normal((size, size, channels), dtype=np.float32)
     return uv, tex
+
+
+def scattered_triangles(seed: int, n_tris: int, H: int, W: int, size: float) -> Scene:
+    """One view of n_tris independent triangles (own vertices each) scattered
+    uniformly over an H x W image: each triangle is a random triangle within
+    a size x size pixel box, at a random depth in [1, 10], with RGB vertex
+    colours.  Consecutive triangles land far apart, so every group of a few
+    hundred of them touches thousands of distinct tiles -- the regime where
+    the binning passes' per-workgroup tile tables fill up."""
+    rng = np.random.default_rng(seed)
+    centre = rng.uniform([0, 0], [W, H], size=(n_tris, 2))
+    corner = rng.uniform(-size / 2, size / 2, size=(n_tris, 3, 2))
+    xy = (centre[:, None, :] + corner).reshape(-1, 2)
+    z = np.repeat(rng.uniform(1.0, 10.0, size=n_tris), 3) * (1.0 + 0.01 * rng.uniform(-1, 1, size=3 * n_tris))
+    v = np.concatenate([xy, z[:, None]], 1).astype(np.float32)
+    tri = np.arange(3 * n_tris, dtype=np.int32).reshape(n_tris, 3)
+    col = rng.uniform(0, 1, size=(3 * n_tris, 3)).astype(np.float32)
+    return _pack(f"scattered-{n_tris}-{W}x{H}", [(v, tri, 0, 0, H, W)], [col], False, False)

@@ -215,7 +215,7 @@ def test_calls_reject_null_arguments_before_any_launch(L):
     assert L.mer_texture(p, fake, None, None, 2, fake, 4, 4, 3, fake, None) == -1
     assert L.mer_texture_bwd(p, fake, None, fake, 2, fake, 4, 4, 3, None, fake, fake, fake, None) == -1
     assert L.mer_texture_bwd(p, fake, None, fake, 2, fake, 4, 4, 3, fake, fake, fake, None, None) == -2
-    assert L.mer_status(p, None, None, (ctypes.c_int64 * 4)()) == -2
+    assert L.mer_status(p, None, None, (ctypes.c_int64 * 6)()) == -2
     assert L.mer_plan_init(None, 1, None, p) == -1
 
 
