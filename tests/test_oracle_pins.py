@@ -494,6 +494,72 @@ def test_p10_icosphere_translation():
     assert np.linalg.norm(ana - fd) / np.linalg.norm(fd) <= _tol_from_paper(), (ana, fd)
 
 
+def _area_derivative(v):
+    """Closed form d(area)/d(x_k, y_k) [3, 2] of the continuous triangle v:
+    area = |D| / 2, D = (x1 - x0)(y2 - y0) - (x2 - x0)(y1 - y0)."""
+    x, y = v[:, 0].astype(np.float64), v[:, 1].astype(np.float64)
+    D = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0])
+    return np.sign(D) / 2 * np.array([[y[1] - y[2], x[2] - x[1]], [y[2] - y[0], x[0] - x[2]],
+                                      [y[0] - y[1], x[1] - x[0]]])
+
+
+def _single_vertex_case(scale):
+    """One constant-colour triangle over background, its vertices at depths
+    1, 8 and 3 (strong perspective), g = 1: L is the number of covered pixel
+    centres, whose derivative tends to that of the continuous area."""
+    H = W = 128 * scale
+    v = np.array([[14.3, 10.6, 1.0], [117.2, 31.9, 8.0], [40.7, 118.4, 3.0]], np.float32)
+    v[:, :2] *= scale
+    t = np.array([[0, 1, 2]], np.int32)
+    attr = np.ones((3, 1), np.float32)
+    g = np.ones((H * W, 1))
+    tid = oracle.rasterize(v, t, H, W)
+    img = oracle.interpolate(attr, v, t, H, W, tid)
+    gv, frag = oracle.edge_grad(v, t, H, W, tid, img, g, want_frag=True)
+    _, gv_o = oracle.interpolate_bwd(attr, v, t, H, W, tid, g)
+    return v, H, W, gv + gv_o, frag
+
+
+def test_p10b_single_vertex_motion_uses_screen_weights():
+    """Reading C14 (Sec. 4.2, last paragraph: fragment gradients reach the
+    vertices through the interpolator's backward function): weights are the
+    screen barycentrics of the pixel's triangle at its centre.  Moving one
+    vertex of a triangle moves each point of its edges by the screen-linear
+    share of that vertex, so dL/d(vertex x, y) must tend to the closed-form
+    derivative of the triangle's area.  The oracle meets it within 2 % at
+    256^2 (the method's discretisation error, which halves per doubling of
+    the resolution); weighting the same fragment gradients with the
+    perspective-correct barycentrics instead -- the alternative reading --
+    misses every component by more than 6 times that tolerance."""
+    tol = 0.02
+    errs = {}
+    for scale in (1, 2):
+        v, H, W, gv, frag = _single_vertex_case(scale)
+        dA = _area_derivative(v)
+        errs[scale] = np.abs(gv[:, :2] - dA) / np.abs(dA)
+        assert np.abs(gv[:, 2]).max() <= 1e-9 * np.abs(dA).max()  # constant colour: no depth term
+    assert errs[2].max() <= tol, errs[2]
+    assert errs[2].max() <= 0.6 * errs[1].max()  # first order in the pixel size
+    # the alternative reading on the same fragment gradients (test-side, from
+    # the unsnapped vertices in binary64)
+    v, H, W, gv, frag = _single_vertex_case(2)
+    x, y, z = (v[:, k].astype(np.float64) for k in range(3))
+    pix = np.nonzero(np.abs(frag).sum(1) > 0)[0]
+    px, py = pix % W + 0.5, pix // W + 0.5
+
+    def orient(a, b):
+        return (x[b] - x[a]) * (py - y[a]) - (y[b] - y[a]) * (px - x[a])
+
+    D = (x[1] - x[0]) * (y[2] - y[0]) - (x[2] - x[0]) * (y[1] - y[0])
+    beta = np.stack([orient(1, 2), orient(2, 0), orient(0, 1)], 1) / D
+    b = (beta / z) / (beta / z).sum(1, keepdims=True)
+    dA = _area_derivative(v)
+    mutant = np.einsum("pk,pc->kc", b, frag[pix, :2])
+    assert (np.abs(mutant - dA) / np.abs(dA)).min() >= 6 * tol
+    screen = np.einsum("pk,pc->kc", beta, frag[pix, :2])
+    assert np.abs(screen - gv[:, :2]).max() <= 1e-3 * np.abs(dA).max()  # the same scatter, unsnapped
+
+
 @pytest.mark.parametrize("flags", [2, 4])
 def test_p10_intersection_depth_per_axis_vs_fd(flags):
     """Depth shift (in 1/z) of one of two intersecting triangles: the
