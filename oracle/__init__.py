@@ -229,7 +229,21 @@ def _view_slices(scene, i):
     return vw, vs, ts, ats
 
 
-def forward(scene, views=None):
+def _each_view(fn, views, threads):
+    """fn(i) for every view, in view order; with threads > 1 the views run on
+    a pool of threads (the C calls release the interpreter lock).  The results
+    come back in view order, so whatever is summed from them is summed in the
+    same order for any thread count."""
+    if threads <= 1:
+        for i in views:
+            yield fn(i)
+        return
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        yield from ex.map(fn, views)
+
+
+def forward(scene, views=None, threads=1):
     """Per-pixel outputs over all views, packed like the GPU buffers.
 
     Returns dict: tri_id i32 [n_px], depth f64 [n_px], bary f64 [n_px,3],
@@ -239,7 +253,8 @@ def forward(scene, views=None):
     n_px = scene.n_px
     out = dict(tri_id=np.full(n_px, -1, np.int32), depth=np.zeros(n_px), bary=np.zeros((n_px, 3)),
                interp=np.zeros((n_px, scene.C_out)), image=np.zeros((n_px, scene.C_e)), backface=np.zeros(n_px))
-    for i in (range(scene.n_views) if views is None else views):
+
+    def one(i):
         vw, vs, ts, ats = _view_slices(scene, i)
         H, W, o = vw["H"], vw["W"], vw["px_off"]
         tid = rasterize(vs, ts, H, W)
@@ -254,19 +269,23 @@ def forward(scene, views=None):
         out["image"][sl, :scene.C_out] = it
         if scene.mask_channel:
             out["image"][sl, scene.C_out] = (tid >= 0).astype(np.float64)
+
+    for _ in _each_view(one, range(scene.n_views) if views is None else views, threads):
+        pass
     return out
 
 
-def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None):
+def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None, threads=1):
     """Fused backward over all views: g_v [sum V_view, 3], g_attr [sum V_attr, C_a].
 
     ``g_img`` is dL/d(image) [n_px, C_e]; its first C_out channels are also
-    dL/d(interpolated attributes).
+    dL/d(interpolated attributes).  Per-view sums are added in view order.
     """
     g_img = np.asarray(g_img, np.float64)
     g_v = np.zeros((scene.v.shape[0], 3))
     g_attr = np.zeros((scene.attr.shape[0], scene.C_a))
-    for i in (range(scene.n_views) if views is None else views):
+
+    def one(i):
         vw, vs, ts, ats = _view_slices(scene, i)
         H, W, o = vw["H"], vw["W"], vw["px_off"]
         sl = slice(o, o + H * W)
@@ -278,6 +297,9 @@ def backward(scene, fwd, g_img, flags=0, edge=True, interp=True, views=None):
         if interp:
             interpolate_bwd(ats, vs, ts, H, W, tid, np.ascontiguousarray(g_img[sl, :scene.C_out]),
                             scene.append_z, g_attr=ga, g_v=gv)
+        return vw, gv, ga
+
+    for vw, gv, ga in _each_view(one, range(scene.n_views) if views is None else views, threads):
         g_v[vw["v_off"]: vw["v_off"] + vw["n_v"]] += gv
         g_attr[vw["a_off"]: vw["a_off"] + vw["n_v"]] += ga
     return g_v, g_attr
