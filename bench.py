@@ -8,10 +8,10 @@ gradient 2 (I - T) is formed inside the backward kernel.
 Batched = all views of the workload in one captured HIP graph; per-view =
 the same calls issued view by view without a graph.
 
-With ``--extras`` it also times, on the same pixels and outside the step's
-timed region, the forward-mode image tangent (field ``jvp``) and deferred
-texturing with an 8-channel 1024^2 texture, forward and adjoint (field
-``texture``).
+It also times, on the same pixels and outside the step's timed region, the
+forward-mode image tangent (field ``jvp``) and deferred texturing with an
+8-channel 1024^2 texture, forward and adjoint (field ``texture``);
+``--no-extras`` skips them.
 
 The roofline object is for the backward sweep: algorithmic bytes over its
 measured launch time against HBM peak, the HBM bytes from stored rocprofv3
@@ -338,8 +338,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
-    ap.add_argument("--extras", action="store_true",
-                    help="also time the forward-mode image tangent and the texture sampler on the step's pixels")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the timings of the forward-mode image tangent and the texture sampler")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (3 times), to scale HBM "
                          "byte counters, and exit")
@@ -414,7 +414,7 @@ def main():
     kt = kernel_times(st, max(3, min(args.steps, 10)), stream)
     log(f"[bench] per-call ms: {kt}")
     extras = {}
-    if args.extras:
+    if not args.no_extras:
         jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
         log(f"[bench] forward-mode image tangent: {jvp_ms:.3f} ms per call")
         tex_ms = texture_time(st, max(3, min(args.steps, 10)), stream)
