@@ -14,10 +14,6 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # The texture sampler's tests run after every other test: a run stopped
-    # by -x at one of them still reports the rasterizer, the backward, the
-    # forward mode and the vertex transform.
-    items.sort(key=lambda item: "texture" in item.nodeid.lower())
     if not any("gpu" in item.keywords for item in items):
         return
     import torch
