@@ -373,6 +373,30 @@ def transform(v_world, R, C, f, cx, cy, w_off, views):
     return out
 
 
+def transform32(v_world, R, C, f, cx, cy, w_off, views):
+    """The same map in binary32, one rounding per operation in the order the
+    library documents for its transform (camera parameters rounded to
+    binary32 first): d = p_world - C, p_cam,r = (R_r0 d_0 + R_r1 d_1) + R_r2 d_2,
+    x = (f p_x) / p_z + cx, y = (f p_y) / p_z + cy, z = p_z.  Snapping the
+    screen vertices to 1/256 px is an integer decision taken on these values,
+    so a chain that feeds the rasterizer from the transform compares its
+    index image against this form.  [sum n_v, 3] float32."""
+    V = np.asarray(views, np.int64)
+    vw = np.asarray(v_world, np.float32)
+    out = np.zeros((max([int(r[0] + r[4]) for r in V] + [0]), 3), np.float32)
+    for i, r in enumerate(V):
+        v_off, n_v = int(r[0]), int(r[4])
+        Ri = np.asarray(R[i], np.float64).astype(np.float32)
+        Ci = np.asarray(C[i], np.float64).astype(np.float32)
+        fi, cxi, cyi = np.float32(f[i]), np.float32(cx[i]), np.float32(cy[i])
+        d = vw[int(w_off[i]): int(w_off[i]) + n_v] - Ci
+        pc = [((Ri[k, 0] * d[:, 0]) + (Ri[k, 1] * d[:, 1])) + (Ri[k, 2] * d[:, 2]) for k in range(3)]
+        out[v_off: v_off + n_v, 0] = (fi * pc[0]) / pc[2] + cxi
+        out[v_off: v_off + n_v, 1] = (fi * pc[1]) / pc[2] + cyi
+        out[v_off: v_off + n_v, 2] = pc[2]
+    return out
+
+
 def transform_bwd(v_world, R, C, f, cx, cy, w_off, views, g_screen):
     """dL/d(world vertices) [n_world, 3]: for every view and vertex, the
     transpose of the projection's Jacobian applied to dL/d(screen vertex),

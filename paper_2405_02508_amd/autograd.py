@@ -11,7 +11,7 @@ fused micro-edge + interpolation sweep once.
 Screen vertices are per view (rows v_off .. v_off + n_v of ``v``).
 ``Transform`` (the vertex transform module) makes them from world vertices
 and one pinhole camera per view, and its backward reduces the per-view
-screen gradients to world space; ``project`` does the same with torch ops.
+screen gradients to world space.
 """
 from __future__ import annotations
 
@@ -24,8 +24,9 @@ class Renderer:
     """Plan, workspace and topology for a fixed view table."""
 
     def __init__(self, views_i64, tri, device="cuda", tile=(8, 8), small_px=0, bin_cap=0,
-                 append_z=False, mask_channel=False, store_bary=True):
-        self.ctx = mer.Context(views_i64, device=device, tile=tile, bin_cap=bin_cap, small_px=small_px)
+                 append_z=False, mask_channel=False, store_bary=True, big_tiles=0):
+        self.ctx = mer.Context(views_i64, device=device, tile=tile, bin_cap=bin_cap, small_px=small_px,
+                               big_tiles=big_tiles)
         self.tri = tri if isinstance(tri, torch.Tensor) else torch.from_numpy(tri).to(device)
         self.n_px = self.ctx.n_px
         self.append_z = bool(append_z)
@@ -196,17 +197,6 @@ class RenderStep(torch.autograd.Function):
 def render(v, attr, r: Renderer, flags: int = 0):
     """Fused forward (image, tri_id, depth); gradients flow to v and attr."""
     return RenderStep.apply(v, attr, r, flags)
-
-
-def project(v_world, R, C, f, cx, cy):
-    """World points [V,3] -> per-view screen vertices [n_cam * V, 3] (torch ops,
-    differentiable): camera frame rows R [n,3,3], centres C [n,3], focal f
-    [n], principal point (cx, cy) [n]."""
-    pc = torch.einsum("nij,vj->nvi", R, v_world) - torch.einsum("nij,nj->ni", R, C)[:, None, :]
-    z = pc[..., 2]
-    x = f[:, None] * pc[..., 0] / z + cx[:, None]
-    y = f[:, None] * pc[..., 1] / z + cy[:, None]
-    return torch.stack([x, y, z], -1).reshape(-1, 3)
 
 
 def back_face_image(r: Renderer, v, tid, flags: int = 0):

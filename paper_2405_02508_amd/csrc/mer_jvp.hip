@@ -10,10 +10,6 @@
 #include "mer_internal.h"
 #include "mer_tiletri.h"
 
-#ifndef JVP_TS
-#define JVP_TS 8
-#endif
-
 namespace mer {
 
 // Screen barycentrics e_k / |D| at pixel (px, py) of snapped triangle s.
@@ -222,10 +218,10 @@ int launch_jvp(const mer_plan* P, const mer_view* views, const float* v, const i
                const float* attr, const float* dattr, int C_a, int append_z, const float* img, int C_e,
                const float* dv, int flags, float* dimg, void* ws, hipStream_t st) {
   long long* tab = (long long*)((char*)ws + P->off_bviewtab);
-  // JVP_TS x JVP_TS tile prefix per view; the rasterizer's status words are
-  // left alone.  A view has at most (16 / JVP_TS)^2 times as many of these
-  // tiles as 16x16 ones, so that many workgroups per 16x16 tile cover them all.
-  constexpr int TS = JVP_TS, lg = TS == 16 ? 4 : 3;
+  // 8x8 tile prefix per view (one wave per tile); the rasterizer's status
+  // words are left alone.  A view has at most 4 times as many of these tiles
+  // as 16x16 ones, so 4 workgroups per 16x16 tile cover them all.
+  constexpr int TS = 8, lg = 3;
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, lg, lg, tab, tab + (P->n_views + 1),
                      (long long*)nullptr);
   const long long grid = P->total_btiles * (16 / TS) * (16 / TS);

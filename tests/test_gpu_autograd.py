@@ -61,12 +61,25 @@ def test_modules_compose_to_the_fused_step():
     assert rel_l2(gv1.cpu().numpy(), ref["g_v"]) <= 1e-5
 
 
+def torch_projection(v_world, R, C, f, cx, cy):
+    """World points [V,3] -> per-view screen vertices [n_cam * V, 3] with
+    torch ops (differentiable): camera frame rows R [n,3,3], centres C
+    [n,3], focal f [n], principal point (cx, cy) [n]."""
+    import torch
+    pc = v_world[None, :, :] @ R.transpose(1, 2).contiguous() - (R @ C[:, :, None])[:, :, 0][:, None, :]
+    z = pc[..., 2]
+    x = f[:, None] * pc[..., 0] / z + cx[:, None]
+    y = f[:, None] * pc[..., 1] / z + cy[:, None]
+    return torch.stack([x, y, z], -1).reshape(-1, 3)
+
+
 def test_world_space_gradient_through_projection():
     """Per-view screen gradients reduce to world space through a torch
     projection in front of RenderStep (config-3-like multi-view rig)."""
     import torch
 
-    from paper_2405_02508_amd.autograd import Renderer, project, render
+    from paper_2405_02508_amd.autograd import Renderer, render
+    project = torch_projection
     say("[autograd] world-space projection, 4 views")
     vs, fs = scenes.icosphere(12)
     Vw = vs * np.array([0.09, 0.12, 0.11])

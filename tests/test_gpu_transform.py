@@ -48,6 +48,10 @@ def test_transform_and_backward_match_the_oracle(k):
         pp[row[0]: row[0] + row[4], 0] = abs(w["cx"][i])
         pp[row[0]: row[0] + row[4], 1] = abs(w["cy"][i])
     assert np.all(np.abs(out - ref) <= 1e-5 * np.maximum(np.maximum(1.0, np.abs(ref)), pp))
+    # and bit for bit the binary32 form, one rounding per operation in the
+    # documented order (what the rasterizer then snaps)
+    ref32 = oracle.transform32(w["v"], w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], s.views)
+    assert np.array_equal(out, ref32), f"{int((out != ref32).sum())} values differ from the binary32 transform"
     assert rel_l2(gw, g_ref) <= 1e-5
 
 
@@ -68,10 +72,13 @@ def test_world_step_through_autograd_matches_the_oracle():
     img, tid, _ = render(v, attr, r)
     g_img = scenes.image_grad(s, 3)
     (img * to_dev(g_img)).sum().backward()
-    # oracle on the same screen vertices (the transform's own parity is the
-    # test above): forward, fused backward to the screen vertices, then the
+    # the oracle's own chain: its binary32 transform (the form whose values
+    # the rasterizer snaps; the GPU's screen vertices must equal it bit for
+    # bit), forward, fused backward to the screen vertices, then the
     # transform's backward
-    s2 = dataclasses.replace(s, v=v.detach().cpu().numpy())
+    v_ref = oracle.transform32(w["v"], w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], s.views)
+    assert np.array_equal(v.detach().cpu().numpy(), v_ref), "screen vertices differ from the binary32 transform"
+    s2 = dataclasses.replace(s, v=v_ref)
     f = oracle.forward(s2)
     assert np.array_equal(tid.cpu().numpy(), f["tri_id"])
     gs, _ = oracle.backward(s2, f, g_img)

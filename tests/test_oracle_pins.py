@@ -747,6 +747,22 @@ def test_p14_points_on_one_ray_share_a_pixel():
     np.testing.assert_allclose(b[:, 2], s * a[:, 2], rtol=1e-12)
 
 
+def test_p14_binary32_transform_rounds_the_binary64_one():
+    """The binary32 form of the transform (the one whose snapped vertices
+    the rasterizer sees) is the binary64 map up to a few roundings."""
+    R, C, f, cx, cy = _cams(3, 5)
+    w = np.concatenate([_points_in_front(R[i], C[i], 200, 6 + i) for i in range(3)]).astype(np.float32)
+    V = _views_for(3, 200)
+    w_off = np.array([0, 200, 400], np.int64)
+    a = oracle.transform(w, R, C, f, cx, cy, w_off, V)
+    b = oracle.transform32(w, R, C, f, cx, cy, w_off, V)
+    assert b.dtype == np.float32
+    # pixel coordinates: relative to the principal point's scale (f x / z and
+    # cx of similar size can cancel); depth relative to itself
+    np.testing.assert_allclose(b[:, :2], a[:, :2], rtol=0, atol=4e-6 * np.abs(a[:, :2]).max())
+    np.testing.assert_allclose(b[:, 2], a[:, 2], rtol=1e-6)
+
+
 def test_p14_backward_matches_central_differences_and_sums_views():
     R, C, f, cx, cy = _cams(3, 8)
     n = 12
