@@ -21,17 +21,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+# reference kernels for the rooflines (copy, float atomics): their own library
+PEAK_SOURCES = ["mer_peak.hip"]
+PEAK_OUT = os.path.join(HERE, "libmer_peak.so")
+
+
+def _hipcc(sources, out, verbose):
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *FLAGS, "-o", tmp, *[os.path.join(CSRC, s) for s in sources]]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed")
     if verbose:
         sys.stderr.write(r.stderr)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(PEAK_SOURCES, PEAK_OUT, verbose)
+    return _hipcc(SOURCES, OUT, verbose)
 
 
 if __name__ == "__main__":

@@ -227,3 +227,22 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         mer.lib()
     with pytest.raises(mer.MerError, match="missing"):
         mer.plan_init(_views([[0, 0, 0, 0, 3, 1, 8, 8]]))
+
+
+def test_peak_library_exports_what_its_header_declares():
+    from paper_2405_02508_amd import peak
+    if not os.path.exists(peak.LIB_PATH):
+        from paper_2405_02508_amd import build
+        build.build()
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "mer_peak.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(mer_peak_[a-z0-9_]+)\s*\(", src)))
+    assert set(names) == set(peak.SYMBOLS)
+    out = subprocess.run(["nm", "-D", "--defined-only", peak.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (mer_peak_\w+)", out))
+    L = peak.lib()
+    for name in names:
+        assert name in exported and hasattr(L, name)
+    # argument checks return before anything is enqueued (no GPU needed)
+    assert L.mer_peak_copy(None, None, 16, None) == -1
+    assert L.mer_peak_atomic_add(None, 16, 256, 1, None) == -1
+    assert L.mer_peak_atomic_add(ctypes.c_void_p(256), 16, 100, 1, None) == -1
