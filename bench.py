@@ -37,7 +37,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 WORKLOADS = {
     4: "batched: 256 displaced-icosphere scenes (1k-200k tris, 10% intersecting pairs), 128-1024 px square",
@@ -226,6 +225,81 @@ def texture_time(st, iters, stream, size=1024, channels=8):
     return res
 
 
+def autograd_time(s, tuning, dev, steps, warmup, stream, lr=1e-9):
+    """The autograd form of the step on world-space geometry (the vertex
+    transform module in front): Transform -> RenderStep (one call: raster,
+    resolve, interpolation, EdgeGrad identity) -> L2 loss against a seeded
+    target in torch -> loss.backward() (one fused sweep, then the transform's
+    backward reducing the per-view screen gradients to world space) -> an
+    SGD update of the world vertices and attributes.  Eager, HIP events on
+    the stream; returns ms per step."""
+    import torch
+
+    from paper_2405_02508_amd import mer
+    from paper_2405_02508_amd.autograd import Renderer, Transform, render
+    w = s.meta["world"]
+    r = Renderer(s.views, torch.from_numpy(s.tri).to(dev), device=dev, tile=tuple(tuning["tile"]),
+                 small_px=tuning["small_px"], bin_cap=tuning["bin_cap"], big_tiles=tuning["big_tiles"],
+                 append_z=s.append_z, mask_channel=s.mask_channel, store_bary=not s.recompute)
+    cams = mer.Cameras(s.views, w["R"], w["C"], w["f"], w["cx"], w["cy"], w["w_off"], device=dev)
+    vw = torch.from_numpy(w["v"]).to(dev).requires_grad_(True)
+    attr = torch.from_numpy(s.attr).to(dev).requires_grad_(True)
+    target = torch.rand(s.n_px, s.C_e, generator=torch.Generator(device=dev).manual_seed(9), device=dev)
+
+    def step():
+        v = Transform.apply(vw, cams, r)
+        img, _, _ = render(v, attr, r)
+        loss = ((img - target) ** 2).sum()
+        loss.backward()
+        with torch.no_grad():
+            vw.sub_(lr * vw.grad)
+            attr.sub_(lr * attr.grad)
+            vw.grad.zero_()
+            attr.grad.zero_()
+
+    for _ in range(max(1, warmup)):
+        step()
+    return time_region(step, steps, stream)
+
+
+def peak_rates(dev, stream, footprint_floats, copy_bytes=1 << 30):
+    """Measured reference rates on this GPU (libmer_peak.so): a plain
+    streaming copy of copy_bytes (GB/s counting read + write), and float
+    atomic adds into a buffer of the workload's gradient footprint and into
+    a 256 MiB buffer (atomics/s).  Best of 5 launches each, HIP events."""
+    import torch
+
+    from paper_2405_02508_amd import peak
+
+    def best(fn, reps=5):
+        fn()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return min(t)
+
+    n = copy_bytes // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms_copy = best(lambda: peak.copy(src, dst))
+    del src, dst
+    lanes, per_lane = 256 * 8192, 32
+    out = {"copy_GBps": round(2 * copy_bytes / ms_copy / 1e6, 1)}
+    for name, fp in (("footprint", int(footprint_floats)), ("256MiB", 1 << 26)):
+        buf = torch.zeros(fp, dtype=torch.float32, device=dev)
+        ms = best(lambda: peak.atomic_add(buf, fp, lanes, per_lane))
+        out[f"atomic_Gops_{name}"] = round(lanes * per_lane / ms / 1e6, 2)
+        del buf
+    out["footprint_floats"] = int(footprint_floats)
+    torch.cuda.empty_cache()
+    return out
+
+
 def algorithmic_bytes(s, kernel, channels=8, tex_bytes=1024 * 1024 * 8 * 4):
     """Bytes the method must move per launch (model stated in the design notes)."""
     n_px = s.n_px
@@ -259,6 +333,8 @@ def algorithmic_bytes(s, kernel, channels=8, tex_bytes=1024 * 1024 * 8 * 4):
 # HIP sources that define the backward sweep kernel (its file and the device
 # helpers it includes)
 BACKWARD_SOURCES = ("mer_backward.hip", "mer_device.h")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters.json")
+VALU_PEAK_GIPS = 256 * 4 * 2.4e9 / 4 / 1e9  # wave64 VALU instructions: 4 SIMDs per CU, 4 cycles each
 
 
 def source_hash(names=BACKWARD_SOURCES):
@@ -273,47 +349,97 @@ def source_hash(names=BACKWARD_SOURCES):
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from rocprofv3 FETCH_SIZE / WRITE_SIZE
-    runs (KiB per dispatch, scaled by the same counters of a plain copy of
-    known size), or None when absent or taken on other kernel sources."""
+def stored_counters(workload, kernel):
+    """Per-dispatch rocprofv3 counter figures of `kernel` on `workload`
+    (profiles/counters.json), or None when absent or taken on other sources
+    of the backward kernel."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(COUNTERS_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("src_hash") != source_hash():
         return None
-    e = t.get("workloads", {}).get(str(workload), {}).get(kernel)
-    if not e:
-        return None
-    return int(1024 * (e["fetch_kib"] * t["fetch_scale"] + e["write_kib"] * t["write_scale"]))
+    return t.get("workloads", {}).get(str(workload), {}).get(kernel)
 
 
-VALU_ISSUE_PER_S = 256 * 2.4e9  # wave64 VALU instructions per second: one per CU per cycle
+def backward_roofline(s, workload, launch_ms, covered, pk):
+    """Roofline object of the backward sweep (one launch = every pixel of
+    every view): HBM bytes, VALU issue and float atomics, each as achieved
+    over its peak; `bound` names the largest fraction and the top-level
+    achieved/peak/frac are that one's."""
+    sec = launch_ms * 1e-3
+    ab = algorithmic_bytes(s, "backward")
+    hbm = {"achieved": round(ab / sec / 1e9, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(ab / sec / 1e9 / PEAK_HBM_GBS, 4), "algorithmic_bytes": ab,
+           "measured_copy_GBps": pk["copy_GBps"], "frac_of_copy": round(ab / sec / 1e9 / pk["copy_GBps"], 4)}
+    # (3 position + C_a attribute) gradient values for each of the 3 vertices
+    # of every covered pixel: the contributions the scatter must sum.  As
+    # float atomics they would need contrib / peak seconds; the kernel sums
+    # them in LDS first and issues `issued` atomics (stored counter), which
+    # is what it asks of the atomic units.
+    contrib = covered * 3 * (3 + s.C_a)
+    apk = pk["atomic_Gops_footprint"]
+    atom = {"contributions": contrib, "contributions_per_s": round(contrib / sec / 1e9, 2),
+            "unreduced_frac": round(contrib / sec / 1e9 / apk, 4), "peak": apk, "unit": "Gatomic/s",
+            "issued": None, "achieved": None, "frac": None, "pre_reduction": None}
+    cs = stored_counters(workload, "k_backward")
+    valu = None
+    traffic = None
+    lds = None
+    if cs:
+        if cs.get("valu_instr"):
+            gi = cs["valu_instr"] / sec / 1e9
+            valu = {"valu_instr": cs["valu_instr"], "achieved": round(gi, 1), "peak": VALU_PEAK_GIPS,
+                    "unit": "G wave-instr/s", "frac": round(gi / VALU_PEAK_GIPS, 4),
+                    "per_wave": round(cs["valu_instr"] / cs["waves"], 1) if cs.get("waves") else None}
+        if cs.get("atomics"):
+            atom["issued"] = cs["atomics"]
+            atom["achieved"] = round(cs["atomics"] / sec / 1e9, 2)
+            atom["frac"] = round(cs["atomics"] / sec / 1e9 / apk, 4)
+            atom["pre_reduction"] = round(contrib / cs["atomics"], 2)
+        traffic = cs.get("hbm_bytes")
+        if cs.get("lds_bank_conflict_cycles") is not None:
+            lds = {"bank_conflict_cycles": cs["lds_bank_conflict_cycles"], "lds_instr": cs.get("lds_instr")}
+    parts = {"hbm": hbm, "alu": valu, "atomic": atom if atom["frac"] is not None else None}
+    bound = max((k for k in parts if parts[k]), key=lambda k: parts[k]["frac"])
+    top = parts[bound]
+    return {"kernel": "k_backward", "bound": bound, "achieved": top["achieved"], "peak": top["peak"],
+            "unit": top["unit"], "frac": top["frac"], "traffic": traffic, "hbm": hbm, "valu": valu,
+            "atomic": atom, "lds": lds, "avg_launch_ms": round(launch_ms, 4), "src_hash": source_hash()}
 
 
-def stored_valu_issue(workload, kernel, launch_ms):
-    """Time the kernel's VALU instructions take at the chip's issue rate,
-    and that time over the measured launch, from a stored SQ_INSTS_VALU
-    count (rocprofv3 --pmc); None when absent or taken on other sources."""
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
     try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("src_hash") != source_hash():
-        return None
-    n = t.get("workloads", {}).get(str(workload), {}).get(kernel, {}).get("valu_instr")
-    if not n:
-        return None
-    ms = n / VALU_ISSUE_PER_S * 1e3
-    return {"valu_instr": n, "issue_ms": round(ms, 4), "frac": round(ms / launch_ms, 4)}
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
-def cpu_baseline(scene, budget_s=15.0):
-    """The CPU oracle as it stands (single thread) on a bounded sample of the
-    workload: whole views, forward + backward, until the time budget is used."""
+def host_threads():
+    """Threads for the all-cores oracle run: the CPUs this process may use,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(scene, budget_s=12.0):
+    """The CPU oracle as it stands on a bounded sample of the workload: whole
+    views, forward + backward (rasterize, resolve, interpolate, L2 gradient,
+    edge term, interpolation adjoint).  First one thread until the time
+    budget is used, then the same views on every host core (views on a
+    thread pool; the C calls release the interpreter lock).  The all-cores
+    figure is the reported value."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
     oracle.lib()
     n_views, px = 0, 0
@@ -323,9 +449,36 @@ def cpu_baseline(scene, budget_s=15.0):
         n_views += 1
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = time.perf_counter() - t0
-    return {"value": round(px / dt / 1e6, 4), "unit": "Mpx/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_views} of {scene.n_views} views ({px} px), forward+backward, one thread, {dt:.1f} s"}
+    dt1 = time.perf_counter() - t0
+    threads = host_threads()
+    # at least a few views per thread, so the pool is busy
+    n_all = min(scene.n_views, max(n_views, 4 * threads))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        px_all = sum(ex.map(lambda i: oracle.step_view(scene, i), range(n_all)))
+    dtn = time.perf_counter() - t0
+    return {"value": round(px_all / dtn / 1e6, 4), "unit": "Mpx/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_all} of {scene.n_views} views ({px_all} px), forward+backward, "
+                      f"{threads} threads (views on a thread pool), {dtn:.1f} s",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(px / dt1 / 1e6, 4), "cores": 1,
+                              "sample": f"first {n_views} views ({px} px), {dt1:.1f} s"}}
+
+
+def step_stats(fn, n, stream):
+    """Per-step times (HIP events around each step) over n steps: median,
+    10th and 90th percentile in ms."""
+    import torch
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"n": n, "median": round(float(np.median(ms)), 4), "p10": round(float(np.percentile(ms, 10)), 4),
+            "p90": round(float(np.percentile(ms, 90)), 4)}
 
 
 def main():
@@ -338,11 +491,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-per-view", action="store_true")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the autograd-form step timing")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the timings of the forward-mode image tangent and the texture sampler")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
-                    help="only run a plain device-to-device copy of BYTES bytes (3 times), to scale HBM "
-                         "byte counters, and exit")
+                    help="only run the reference copy kernel (k_copy16) over BYTES bytes (3 times), to check "
+                         "the HBM byte counters against a known transfer, and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
@@ -351,14 +505,15 @@ def main():
     import torch
 
     if args.calibrate_copy:
-        n = args.calibrate_copy // 4
+        from paper_2405_02508_amd import peak
+        n = args.calibrate_copy // 16 * 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         ms = []
         for _ in range(3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            dst.copy_(src)
+            peak.copy(src, dst)
             e1.record()
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
@@ -411,8 +566,11 @@ def main():
         run_batched = st.run
     ms = time_region(run_batched, args.steps, stream)
     log(f"[bench] batched {'graph' if graph else 'eager'}: {ms:.3f} ms/step")
+    stats = step_stats(run_batched, max(50, args.steps), stream)
+    log(f"[bench] per-step ms over {stats['n']} steps: median {stats['median']} p10 {stats['p10']} p90 {stats['p90']}")
     kt = kernel_times(st, max(3, min(args.steps, 10)), stream)
     log(f"[bench] per-call ms: {kt}")
+    covered = int((st.tid >= 0).sum().item())
     extras = {}
     if not args.no_extras:
         jvp_ms = jvp_time(st, max(3, min(args.steps, 10)), stream)
@@ -455,12 +613,29 @@ def main():
         log(f"[bench] per-view eager: {ms_pv:.3f} ms/step")
         del st_pv
 
+    # ---- the autograd form on world-space geometry (vertex transform in front)
+    ag = None
+    if not args.no_autograd and "world" in s.meta:
+        del st
+        torch.cuda.empty_cache()
+        st = None
+        ms_ag = autograd_time(s, tuning, dev, max(3, args.steps // 2), args.warmup, stream)
+        ag = {"ms_per_step": round(ms_ag, 4), "value": round(s.n_px / ms_ag / 1e3, 2), "unit": "Mpx/s",
+              "calls": "Transform -> RenderStep -> torch L2 loss -> backward (fused sweep, transform backward) "
+                       "-> SGD update", "graph": False}
+        log(f"[bench] autograd step (eager): {ms_ag:.3f} ms/step")
+        torch.cuda.empty_cache()
+
+    # ---- reference rates for the rooflines, measured on this GPU
+    grad_floats = s.v.shape[0] * 3 + s.attr.size
+    pk = peak_rates(dev, stream, grad_floats)
+    log(f"[bench] reference rates: {pk}")
+
     # roofline of the dominant single kernel: k_backward, the one kernel of the
     # backward call (plus a ~5 us view-table prep); the rasterize call is a
     # pipeline of eight kernels, none as long as the backward sweep
     dom = "backward"
-    ab = algorithmic_bytes(s, dom)
-    achieved = ab / (kt[dom] * 1e-3) / 1e9
+    roof = backward_roofline(s, args.workload, kt[dom], covered, pk)
     out = {
         "metric": "fwd+bwd Mpixels/s (raster+micro-edge grad), batched vs per-view, err<=1e-5",
         "value": round(s.n_px / ms / 1e3, 2),
@@ -477,18 +652,17 @@ def main():
         "config": {"workload": f"config {args.workload}: {WORKLOADS[args.workload]}", "scene": s.name,
                    "views": s.n_views, "pixels": s.n_px, "view_triangles": int(s.views[:, 5].sum()),
                    "tuning": tuning, "graph": used_graph, "barycentrics": "recomputed" if s.recompute else "stored"},
+        "step_ms": stats,
         "per_view": pv,
+        "autograd_step": ag,
         "per_call_ms": {k: round(v, 4) for k, v in kt.items()},
-        "roofline": {"kernel": "k_backward", "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": stored_traffic(args.workload, "k_backward"),
-                     "valu_issue": stored_valu_issue(args.workload, "k_backward", kt[dom]),
-                     "algorithmic_bytes": ab, "avg_launch_ms": round(kt[dom], 4), "src_hash": source_hash()},
+        "roofline": roof,
+        "reference_rates": pk,
         "cpu_baseline": None,
         **extras,
     }
     if not args.no_cpu:
-        del st
+        st = None
         torch.cuda.empty_cache()
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
