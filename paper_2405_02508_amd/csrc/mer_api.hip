@@ -110,6 +110,10 @@ static bool plan_ok(const mer_plan* P) {
   return P && P->n_views >= 1 && P->ws_bytes > 0 && tile_supported(P->tile_w, P->tile_h);
 }
 
+// The backward calls' scratch inside the plan's workspace.
+static long long* bwd_tab(const mer_plan* P, void* ws) { return (long long*)((char*)ws + P->off_bviewtab); }
+static float* bwd_loss(const mer_plan* P, void* ws) { return (float*)((char*)ws + P->off_bloss); }
+
 int mer_rasterize(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri, int32_t* tri_id,
                   float* depth, float* bary, void* ws, void* stream) {
   if (!plan_ok(P) || !views_dev || !tri_id || (P->total_tris > 0 && (!v || !tri))) return MER_EINVAL;
@@ -167,7 +171,8 @@ int mer_edge_grad(const mer_plan* P, const mer_view* views_dev, const float* v, 
     return MER_EINVAL;
   if (!ws) return MER_EWORKSPACE;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, nullptr, 0, 0, img, g_img, nullptr, 0.f, nullptr, C_e, C_e,
-                              (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, ws, (hipStream_t)stream);
+                              (flags & MER_NO_INTERSECT) | MER_SKIP_INTERP, nullptr, g_v, bwd_tab(P, ws), bwd_loss(P, ws),
+                              (hipStream_t)stream);
 }
 
 int mer_interpolate_bwd(const mer_plan* P, const mer_view* views_dev, const float* attr, int C_a, const float* v,
@@ -180,7 +185,7 @@ int mer_interpolate_bwd(const mer_plan* P, const mer_view* views_dev, const floa
   if (!g_attr && !g_v) return MER_OK;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, nullptr, g_out, nullptr,
                               0.f, nullptr, ld_out,
-                              ld_out, MER_SKIP_EDGE, g_attr, g_v, ws, (hipStream_t)stream);
+                              ld_out, MER_SKIP_EDGE, g_attr, g_v, bwd_tab(P, ws), bwd_loss(P, ws), (hipStream_t)stream);
 }
 
 int mer_backward_fused(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
@@ -193,7 +198,7 @@ int mer_backward_fused(const mer_plan* P, const mer_view* views_dev, const float
   if (!ws) return MER_EWORKSPACE;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, g_img, nullptr, 0.f,
                               nullptr, C_e, C_e, flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr,
-                              g_v, ws, (hipStream_t)stream);
+                              g_v, bwd_tab(P, ws), bwd_loss(P, ws), (hipStream_t)stream);
 }
 
 int mer_backward_l2(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
@@ -209,7 +214,7 @@ int mer_backward_l2(const mer_plan* P, const mer_view* views_dev, const float* v
   if (!ws) return MER_EWORKSPACE;
   return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, nullptr, target, weight,
                               loss, C_e, C_e, flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr,
-                              g_v, ws, (hipStream_t)stream);
+                              g_v, bwd_tab(P, ws), bwd_loss(P, ws), (hipStream_t)stream);
 }
 
 int mer_jvp(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,

@@ -136,13 +136,12 @@ __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, cons
 }
 
 // Segmented inclusive sum over lanes [hir, lir] of one 16-lane row of a
-// wave, with DPP row shifts (row_shr:1, 2, 4, 8).
-template <int CTRL>
-__device__ __forceinline__ float dpp_row_shr(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xf, 0xf, true));
-}
-// m[i] is 1 where the lane 2^i places to the left is in the same run, else 0
-// (so the fused multiply-add below adds either the neighbour or exactly 0).
+// wave: four doubling steps x += m_S * x[lane - S] (S = 1, 2, 4, 8), each one
+// v_fmac_f32 whose first operand is read through a DPP row shift (a lane at
+// the start of its 16-lane row reads 0).  m_S is 1 where the lane S places to
+// the left is in the same run, else 0, so the step adds the neighbour's
+// partial sum or exactly 0.  The s_nop covers the two wait states a DPP read
+// of a register needs after a VALU write to it.
 struct RunMask {
   float m1, m2, m4, m8;
 };
@@ -151,27 +150,39 @@ __device__ __forceinline__ RunMask run_mask(int lir, int hir) {
           lir - 8 >= hir ? 1.f : 0.f};
 }
 __device__ __forceinline__ float seg_sum(float x, const RunMask& m) {
-  x = __builtin_fmaf(dpp_row_shr<0x111>(x), m.m1, x);
-  x = __builtin_fmaf(dpp_row_shr<0x112>(x), m.m2, x);
-  x = __builtin_fmaf(dpp_row_shr<0x114>(x), m.m4, x);
-  x = __builtin_fmaf(dpp_row_shr<0x118>(x), m.m8, x);
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m1));
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m2));
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m4));
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m8));
   return x;
 }
 
 // Backward sweep over 16x16 pixel tiles of one view per workgroup (256
 // threads; wave w holds rows 4w..4w+3, 16 lanes per row).
-//  1. each lane computes its pixel's fragment gradient from the micro-edges
-//     it belongs to (Sec. 4.2-4.4) and its interpolation adjoint (Omega);
-//  2. lanes sum runs of equal triangle along each 16-pixel row (a triangle
+//  1. each lane snaps its pixel's triangle once and computes its exact edge
+//     values, from which it decides which of its four neighbours' centres
+//     the triangle holds; it publishes that 4-bit mask and its triangle id
+//     in LDS.  The first wave does the same for the tile's ring (the 64
+//     pixels just outside it next to its border pixels), each ring pixel's
+//     bit being whether its triangle holds its tile neighbour's centre;
+//  2. each lane takes the micro-edges it belongs to (Sec. 4.2-4.4): a pair's
+//     classification needs "B's triangle holds A's centre" and "A's triangle
+//     holds B's centre", one bit of each side's mask, so no neighbour
+//     triangle is snapped again (intersections, which need both planes'
+//     slopes, snap the neighbour's triangle).  Image and dL/d(image) rows are
+//     read with vector loads;
+//  3. its interpolation adjoint (Omega);
+//  4. lanes sum runs of equal triangle along each 16-pixel row (a triangle
 //     meets a row in one run: it is convex) with a segmented wave reduction;
-//  3. the last lane of each run adds the run's sums into an LDS table keyed
+//     the last lane of each run adds the run's sums into an LDS table keyed
 //     by vertex (a vertex is shared by the runs of several triangles);
-//  4. the workgroup flushes the table with one global float atomic per
+//  5. the workgroup flushes the table with one global float atomic per
 //     (vertex, component).  Vertices that do not fit the table, and
 //     attribute channels beyond kCTab, go straight to global atomics.
 constexpr int kSlots = 256;  // vertex slots per workgroup
 constexpr int kCTab = 8;     // attribute channels reduced in LDS
 constexpr int kNV = 3 + kCTab;
+constexpr int kQ = 256 + 64;  // tile pixels and ring pixels
 
 // Find or claim the slot of vertex `key`; a new slot has its values zeroed
 // and is appended to the occupied list.  -1 when the probe limit is hit.
@@ -192,11 +203,39 @@ __device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, in
   return -1;
 }
 
+// Up to four consecutive floats of a row, with one vector load where the
+// channel count allows it (vec: 4 = rows of a multiple of 4 floats at a
+// 16-byte aligned base, 3 = rows of 3 floats, 0 = one load per float).
+__device__ __forceinline__ float4 row4(const float* __restrict__ a, int vec, int n) {
+  if (vec == 4) return *reinterpret_cast<const float4*>(a);
+  if (vec == 3) {
+    const float3 x = *reinterpret_cast<const float3*>(a);
+    return make_float4(x.x, x.y, x.z, 0.f);
+  }
+  float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+  x.x = a[0];
+  if (n > 1) x.y = a[1];
+  if (n > 2) x.z = a[2];
+  if (n > 3) x.w = a[3];
+  return x;
+}
+__device__ __forceinline__ int row_vec(int C, const void* base) {
+  return C == 3 ? 3 : ((C & 3) == 0 && ((uintptr_t)base & 15) == 0) ? 4 : 0;
+}
+__device__ __forceinline__ float f4(const float4& x, int j) { return j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w; }
+// Two consecutive floats of a row, one 8-byte load when vec2 (rows of an
+// even number of floats at an 8-byte aligned base), else two loads (the
+// second only when n > 1).
+__device__ __forceinline__ float2 row2(const float* __restrict__ a, bool vec2, int n) {
+  if (vec2) return *reinterpret_cast<const float2*>(a);
+  return make_float2(a[0], n > 1 ? a[1] : 0.f);
+}
+
 // L2: dL/d(img) = 2 w (img - target) is formed here instead of read from g.
 // LOSS: w * sum (img - target)^2 over each wave's 64 pixels goes to
 // loss_part[4 tile + wave] (computed last, when few registers are live).
 template <bool L2, bool LOSS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k_backward(const mer_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_backward(const mer_view* __restrict__ views, int n_views,
                                                   const long long* __restrict__ btile_base,
                                                   const float* __restrict__ v, const int32_t* __restrict__ tri,
                                                   const int32_t* __restrict__ tri_id, const float* __restrict__ attr,
@@ -209,6 +248,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   __shared__ float s_val[kSlots * kNV];
   __shared__ int s_list[kSlots];
   __shared__ int s_nocc;
+  // the tile's 256 pixels, then its ring: the 64 pixels just outside it that
+  // are neighbours of its border pixels (16 per side: left, right, up, down)
+  __shared__ int s_t[kQ];
+  __shared__ unsigned char s_cm[kQ];
   for (int i = threadIdx.x; i < kSlots; i += blockDim.x) s_key[i] = -1;
   if (threadIdx.x == 0) s_nocc = 0;
 
@@ -217,67 +260,114 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   const mer_view vw = views[vi];
   const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + 15) >> 4;
+  const int x0 = (int)(local_tile % tiles_x) * 16, y0 = (int)(local_tile / tiles_x) * 16;
   const int lane = threadIdx.x & 63;
-  const int px = (int)(local_tile % tiles_x) * 16 + (lane & 15);
-  const int py = (int)(local_tile / tiles_x) * 16 + (threadIdx.x >> 4);
+  const int lt = threadIdx.x;  // pixel (lt & 15, lt >> 4) of the tile
+  const int lx = lt & 15, ly = lt >> 4;
+  const int px = x0 + lx, py = y0 + ly;
   const bool inside = px < vw.W && py < vw.H;
   const long long p = vw.px_off + (long long)py * vw.W + px;
+  const bool want_edge = !(flags & MER_SKIP_EDGE);
+  const bool want_interp = !(flags & MER_SKIP_INTERP);
+  // image, target and dL/d(image) rows: vector widths (uniform)
+  const int vimg = row_vec(C_e, img), vtar = L2 ? row_vec(C_e, target) : 0;
+  const int vg = L2 ? 0 : (ld_g == C_e ? row_vec(C_e, g) : (((ld_g & 3) == 0 && ((uintptr_t)g & 15) == 0) ? 4 : 0));
+  const bool v2img = (C_e & 1) == 0 && ((uintptr_t)img & 7) == 0;
+  const bool v2tar = L2 && (C_e & 1) == 0 && ((uintptr_t)target & 7) == 0;
+  const bool v2g = !L2 && (ld_g & 1) == 0 && ((uintptr_t)g & 7) == 0;
+
+  // ---- the ring, by the first wave: each lane one ring pixel.  Its id, and
+  // whether its triangle holds the centre of its neighbour in the tile (as
+  // the bit that neighbour looks up: the direction back from the ring pixel)
+  if (want_edge && threadIdx.x < 64) {
+    const int r = threadIdx.x, side = r >> 4, i = r & 15;
+    const int ix = side == 0 ? x0 : side == 1 ? x0 + 15 : x0 + i;  // the tile pixel next to it
+    const int iy = side == 2 ? y0 : side == 3 ? y0 + 15 : y0 + i;
+    const int qx = side == 0 ? x0 - 1 : side == 1 ? x0 + 16 : ix;
+    const int qy = side == 2 ? y0 - 1 : side == 3 ? y0 + 16 : iy;
+    const bool rin = qx >= 0 && qy >= 0 && qx < vw.W && qy < vw.H;
+    int rt = -1;
+    if (rin) {
+      rt = tri_id[vw.px_off + (long long)qy * vw.W + qx];
+      if (rt >= vw.n_t || rt < 0) rt = -1;
+    }
+    unsigned rc = 0;
+    if (rt >= 0 && contains(snap_triangle<false>(v, vw, tri_row(tri, vw, rt)), ix, iy)) rc = 1u << (side ^ 1);
+    s_t[256 + r] = rt;
+    s_cm[256 + r] = (unsigned char)rc;
+  }
+
   int t = -1;
   if (inside) {
     t = tri_id[p];
     if (t >= vw.n_t || t < 0) t = -1;
   }
+  // the id as the neighbours see it (a triangle that does not snap is still
+  // a triangle to them, one that holds no centre); -1 below if it does not
+  const int t_id = t;
   Snap S;
   S.ok = false;
-  if (t >= 0) S = snap_id<false>(v, tri, vw, t);
+  if (t >= 0) S = snap_triangle<false>(v, vw, tri_row(tri, vw, t));
   if (t >= 0 && !S.ok) t = -1;
+  unsigned cm = 0;  // bit d: this triangle holds neighbour d's centre
+  if (want_edge && t >= 0) cm = neighbour_cover(pix_edges(S, px, py));
+  s_t[lt] = t_id;
+  s_cm[lt] = (unsigned char)cm;
+  __syncthreads();
 
-  // ---- micro-edge term: fragment gradient (rx, ry, rq) of this pixel
+  // ---- micro-edge term: fragment gradient (rx, ry, rq) of this pixel.
+  // A background pixel is never the top side of a pair, so it receives
+  // nothing.  Neighbour d: 0 left, 1 right, 2 up, 3 down; q(d) its place in
+  // the tile or the ring.
+  auto nq = [&](int dir) -> int {
+    if (dir == 0) return lx > 0 ? lt - 1 : 256 + ly;
+    if (dir == 1) return lx < 15 ? lt + 1 : 256 + 16 + ly;
+    if (dir == 2) return ly > 0 ? lt - 16 : 256 + 32 + lx;
+    return ly < 15 ? lt + 16 : 256 + 48 + lx;
+  };
   float rx = 0.f, ry = 0.f, rq = 0.f;
-  // a background pixel is never the top side of a pair, so it receives nothing.
-  // First the cheap part: which of the four neighbours differ (bit dir of
-  // `pend`); then the wave iterates only as often as its busiest lane has
-  // differing neighbours, each lane taking its next pending pair.
-  unsigned pend = 0;
-  int tn4[4] = {-1, -1, -1, -1};
-  if (t >= 0 && !(flags & MER_SKIP_EDGE)) {
-#pragma unroll
-    for (int dir = 0; dir < 4; ++dir) {
-      const int nx = px + (dir == 0 ? -1 : dir == 1 ? 1 : 0);
-      const int ny = py + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
-      if (nx < 0 || ny < 0 || nx >= vw.W || ny >= vw.H) continue;
-      int tn = tri_id[vw.px_off + (long long)ny * vw.W + nx];
-      if (tn >= vw.n_t || tn < 0) tn = -1;
-      tn4[dir] = tn;
-      if (tn != t) pend |= 1u << dir;
-    }
+  unsigned pend = 0;  // bit d: neighbour d is in the view and shows another id
+  if (want_edge && t >= 0) {
+    pend |= (px > 0 && s_t[nq(0)] != t) ? 1u : 0u;
+    pend |= (px + 1 < vw.W && s_t[nq(1)] != t) ? 2u : 0u;
+    pend |= (py > 0 && s_t[nq(2)] != t) ? 4u : 0u;
+    pend |= (py + 1 < vw.H && s_t[nq(3)] != t) ? 8u : 0u;
   }
+  // the wave takes as many rounds as its busiest lane has such neighbours
 #pragma unroll 1
   while (__ballot(pend != 0)) {
     if (pend == 0) continue;
     const int dir = __builtin_ctz(pend);
     pend &= pend - 1;
-    const int tn = dir == 0 ? tn4[0] : dir == 1 ? tn4[1] : dir == 2 ? tn4[2] : tn4[3];
-    const int nx = px + (dir == 0 ? -1 : dir == 1 ? 1 : 0);
-    const int ny = py + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
-    const long long pn = vw.px_off + (long long)ny * vw.W + nx;
+    const int q = nq(dir);
+    const int tn = s_t[q];
     const bool selfA = dir == 1 || dir == 3;  // self has the smaller coordinate
     const int axis = dir < 2 ? 0 : 1;
+    const int nx = px + (dir == 0 ? -1 : dir == 1 ? 1 : 0), ny = py + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
+    const long long pn = vw.px_off + (long long)ny * vw.W + nx;
     const long long pA = selfA ? p : pn, pB = selfA ? pn : p;
+    // dL/dp = 1/2 sum_c (g_A + g_B)(I_A - I_B), A before B, four channels a load
     float acc = 0.f;
-    const float* ia = img + pA * C_e;
-    const float* ib = img + pB * C_e;
-    if constexpr (L2) {
-      const float* ta = target + pA * C_e;
-      const float* tb = target + pB * C_e;
-      for (int c = 0; c < C_e; ++c) {
-        const float gs = (2.0f * w_l2) * (ia[c] - ta[c]) + (2.0f * w_l2) * (ib[c] - tb[c]);
-        acc += gs * (ia[c] - ib[c]);
+#pragma unroll 1
+    for (int c0 = 0; c0 < C_e; c0 += 4) {
+      const int n = min(4, C_e - c0);
+      const float4 ia = row4(img + pA * C_e + c0, vimg, n), ib = row4(img + pB * C_e + c0, vimg, n);
+      float4 ga, gb;
+      if constexpr (L2) {
+        const float4 ta = row4(target + pA * C_e + c0, vtar, n), tb = row4(target + pB * C_e + c0, vtar, n);
+        ga = make_float4((2.0f * w_l2) * (ia.x - ta.x), (2.0f * w_l2) * (ia.y - ta.y), (2.0f * w_l2) * (ia.z - ta.z),
+                         (2.0f * w_l2) * (ia.w - ta.w));
+        gb = make_float4((2.0f * w_l2) * (ib.x - tb.x), (2.0f * w_l2) * (ib.y - tb.y), (2.0f * w_l2) * (ib.z - tb.z),
+                         (2.0f * w_l2) * (ib.w - tb.w));
+      } else {
+        ga = row4(g + pA * ld_g + c0, vg, n);
+        gb = row4(g + pB * ld_g + c0, vg, n);
       }
-    } else {
-      const float* ga = g + pA * ld_g;
-      const float* gb = g + pB * ld_g;
-      for (int c = 0; c < C_e; ++c) acc += (ga[c] + gb[c]) * (ia[c] - ib[c]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= n) break;
+        acc += (f4(ga, j) + f4(gb, j)) * (f4(ia, j) - f4(ib, j));
+      }
     }
     const float dLdp = 0.5f * acc;
     if (tn < 0) {
@@ -286,29 +376,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
       else ry += dLdp;
       continue;
     }
-    const Snap Sn = snap_id<false>(v, tri, vw, tn);
-    Snap SA, SB;  // by value: a conditional reference would force the structs to scratch
-    if (selfA) {
-      SA = S;
-      SB = Sn;
-    } else {
-      SA = Sn;
-      SB = S;
-    }
-    const int ax_ = selfA ? px : nx, ay_ = selfA ? py : ny;
-    const int bx_ = selfA ? nx : px, by_ = selfA ? ny : py;
-    const bool cA = contains(SB, ax_, ay_);  // B's triangle holds A's centre
-    const bool cB = contains(SA, bx_, by_);  // A's triangle holds B's centre
-    if (!cA && !cB) continue;                // adjacent: nothing
-    if (cA != cB) {
-      if (cA == selfA) {                     // the contained side is on top
+    // mine: this triangle holds the neighbour's centre; theirs: the
+    // neighbour's triangle holds this centre (a bit of its mask)
+    const bool mine = (cm >> dir) & 1u;
+    const bool theirs = (s_cm[q] >> (dir ^ 1)) & 1u;
+    if (!mine && !theirs) continue;  // adjacent: nothing
+    if (mine != theirs) {
+      // the side whose centre the other triangle holds is on top
+      if (theirs) {
         if (axis == 0) rx += dLdp;
         else ry += dLdp;
       }
       continue;
     }
     if (flags & MER_NO_INTERSECT) continue;
-    const float sA = plane_slope(SA, axis), sB = plane_slope(SB, axis);
+    // intersection: both planes' slopes along the pair's axis
+    const Snap Sn = snap_triangle<false>(v, vw, tri_row(tri, vw, tn));
+    const float sS = plane_slope(S, axis), sN = plane_slope(Sn, axis);
+    const float sA = selfA ? sS : sN, sB = selfA ? sN : sS;
     const float dlt = sB - sA;
     if (!(dlt > 0.f) || !isfinite(dlt)) continue;
     const float u = dLdp / dlt;
@@ -333,15 +418,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   pb.b[0] = pb.b[1] = pb.b[2] = 0.f;
   pb.Wq = 1.f;
   if (t >= 0) pb = pixel_bary(S, px, py);
-  float gx[3], gy[3], gz[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float qk = t >= 0 ? S.q[k] : 0.f;
-    gx[k] = pb.beta[k] * rx;
-    gy[k] = pb.beta[k] * ry;
-    gz[k] = pb.beta[k] * rq * (-(qk * qk));
-  }
-  __syncthreads();  // keys cleared
+
   int slot[3] = {-1, -1, -1};
   if (emit) {
 #pragma unroll
@@ -349,50 +426,61 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
   }
   __syncthreads();  // every slot this tile uses is claimed and zeroed
 
-  // ---- interpolation adjoint and Omega
-  if (!(flags & MER_SKIP_INTERP)) {
-    // this pixel's dL/d(image) row
+  // ---- interpolation adjoint and Omega.  Both terms move vertex k's x and y
+  // by beta_k times a per-pixel vector (the fragment gradient, and minus the
+  // screen gradient of dL/d(beta) for Omega), so they are summed per pixel
+  // first; the 1/z part differs per vertex (dw).
+  float fx = rx, fy = ry;
+  float dw[3] = {0.f, 0.f, 0.f};
+  float gzc = 0.f;  // dL/d(interpolated z)
+  if (want_interp) {
     const long long pg = t >= 0 ? p : 0;
-    const float* gp = L2 ? img + pg * C_e : g + pg * ld_g;
-    const float* tp = L2 ? target + pg * C_e : nullptr;
-    auto gown = [&](int c) -> float {
-      if constexpr (L2) return (2.0f * w_l2) * (gp[c] - tp[c]);
-      else return gp[c];
-    };
-    long long arow[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) arow[k] = t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0;
+    const int C = C_a + append_z;
+    const int va = row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : row_vec(C_a, attr) == 3 ? 3 : 0;
     float G[3] = {0.f, 0.f, 0.f};
-    for (int c = 0; c < C_a; ++c) {  // uniform trip count: every lane joins the reductions
-      const float gc = t >= 0 ? gown(c) : 0.f;
+    for (int c0 = 0; c0 < C_a; c0 += 4) {  // uniform trip count: every lane joins the reductions
+      const int n = min(4, C_a - c0);
+      float4 gc4;
+      if constexpr (L2) {
+        const float4 i4 = row4(img + pg * C_e + c0, vimg, n), t4 = row4(target + pg * C_e + c0, vtar, n);
+        gc4 = make_float4((2.0f * w_l2) * (i4.x - t4.x), (2.0f * w_l2) * (i4.y - t4.y), (2.0f * w_l2) * (i4.z - t4.z),
+                          (2.0f * w_l2) * (i4.w - t4.w));
+      } else {
+        gc4 = row4(g + pg * ld_g + c0, vg, n);
+      }
+      if (t < 0) gc4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        if (t >= 0) G[k] += gc * attr[arow[k] + c];
-        if (g_attr) {
-          const float s = seg_sum(pb.b[k] * gc, rm);
-          if (emit && s != 0.f) {
-            if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], s);
-            else atomicAdd(g_attr + arow[k] + c, s);
+        const float4 a4 = row4(attr + (t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0) + c0, va, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= n) break;
+          const float gc = f4(gc4, j);
+          const int c = c0 + j;
+          G[k] += gc * f4(a4, j);
+          if (g_attr) {
+            const float sm = seg_sum(pb.b[k] * gc, rm);
+            if (emit && sm != 0.f) {
+              if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], sm);
+              else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c, sm);
+            }
           }
         }
       }
     }
     if (t >= 0) {
       if (append_z) {
+        gzc = L2 ? (2.0f * w_l2) * (img[pg * C_e + C_a] - target[pg * C_e + C_a]) : g[pg * ld_g + C_a];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          G[k] += gown(C_a) * S.z[k];
-          gz[k] += pb.b[k] * gown(C_a);
-        }
+        for (int k = 0; k < 3; ++k) G[k] += gzc * S.z[k];
       }
       const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
       const float iW = __builtin_amdgcn_rcpf(pb.Wq);
       float dbeta[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const float dw = (G[k] - Gb) * iW;
-        dbeta[k] = dw * S.q[k];
-        gz[k] += (dw * pb.beta[k]) * (-(S.q[k] * S.q[k]));
+        dw[k] = (G[k] - Gb) * iW;
+        dbeta[k] = dw[k] * S.q[k];
       }
       // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
       const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
@@ -403,17 +491,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
         sx += dbeta[i] * ((float)(-(S.Y[b] - S.Y[a])) * invD);
         sy += dbeta[i] * ((float)(S.X[b] - S.X[a]) * invD);
       }
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        gx[k] += -pb.beta[k] * sx;
-        gy[k] += -pb.beta[k] * sy;
-      }
+      fx -= sx;
+      fy -= sy;
     }
+    (void)C;
   }
   if (g_v) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const float sums[3] = {seg_sum(gx[k], rm), seg_sum(gy[k], rm), seg_sum(gz[k], rm)};
+      const float qk = t >= 0 ? S.q[k] : 0.f;
+      // 1/z part: the fragment's rq and Omega's dw, through d(1/z)/dz = -1/z^2;
+      // the z channel's own interpolation weight b_k
+      const float gzk = (pb.beta[k] * (rq + dw[k])) * (-(qk * qk)) + pb.b[k] * gzc;
+      const float sums[3] = {seg_sum(pb.beta[k] * fx, rm), seg_sum(pb.beta[k] * fy, rm), seg_sum(gzk, rm)};
       if (emit) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
@@ -443,17 +533,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) k
     }
   }
   if constexpr (LOSS) {
-    {
-      float e2 = 0.f;
-      if (inside)
-        for (int c = 0; c < C_e; ++c) {
-          const float d = img[p * C_e + c] - target[p * C_e + c];
-          e2 += d * d;
-        }
+    float e2 = 0.f;
+    if (inside)
+      for (int c = 0; c < C_e; ++c) {
+        const float d = img[p * C_e + c] - target[p * C_e + c];
+        e2 += d * d;
+      }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
-      if (lane == 0) loss_part[4 * tile + (threadIdx.x >> 6)] = w_l2 * e2;
-    }
+    for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o, 64);
+    if (lane == 0) loss_part[4 * tile + (threadIdx.x >> 6)] = w_l2 * e2;
   }
 }
 
@@ -489,9 +577,8 @@ __global__ void __launch_bounds__(1024) k_loss_sum(const float* __restrict__ par
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
                     const float* g, const float* target, float w_l2, float* loss, int C_e, int ld_g, int flags,
-                    float* g_attr, float* g_v, void* ws, hipStream_t st) {
-  long long* tab = (long long*)((char*)ws + P->off_bviewtab);
-  float* bloss = loss ? (float*)((char*)ws + P->off_bloss) : nullptr;
+                    float* g_attr, float* g_v, long long* tab, float* loss_part, hipStream_t st) {
+  float* bloss = loss ? loss_part : nullptr;
   // 16x16 tile prefix per view; the rasterizer's status words are left alone
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(1024), 0, st, views, P->n_views, 4, 4, tab, tab + (P->n_views + 1),
                      (long long*)nullptr);

@@ -208,6 +208,52 @@ __device__ __forceinline__ bool contains(const Snap& s, int px, int py) {
   return covered_at(s, E);
 }
 
+// Exact edge values of snapped triangle s at the centre of pixel (px, py),
+// with their steps to the neighbouring centres.  Ep[k] = sign(D) *
+// orient(v_{k+1}, v_{k+2}, centre) + tl_k, biased by the top-left rule so
+// that a centre is covered iff all three are > 0; one pixel to the right
+// adds dx[k] = 256 A_k, one pixel down dy[k] = 256 B_k, with (A_k, B_k) the
+// inward normal of edge k.
+struct PixEdges {
+  long long Ep[3];
+  long long dx[3], dy[3];
+  int tl;  // bit k: edge k is a top or left edge
+};
+
+__device__ __forceinline__ PixEdges pix_edges(const Snap& s, int px, int py) {
+  PixEdges o;
+  long long E[3];
+  edge_at(s, px, py, E);
+  const bool neg = s.D < 0;
+  o.tl = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const int A = neg ? (s.Y[b] - s.Y[a]) : -(s.Y[b] - s.Y[a]);
+    const int B = neg ? -(s.X[b] - s.X[a]) : (s.X[b] - s.X[a]);
+    const int tl = (A > 0 || (A == 0 && B > 0)) ? 1 : 0;
+    o.tl |= tl << k;
+    o.Ep[k] = E[k] + tl;
+    o.dx[k] = (long long)A * 256;
+    o.dy[k] = (long long)B * 256;
+  }
+  return o;
+}
+
+// Which of the four neighbouring centres the triangle covers: bit d for
+// neighbour d = 0 left, 1 right, 2 up, 3 down (same rule as the rasterizer).
+__device__ __forceinline__ unsigned neighbour_cover(const PixEdges& e) {
+  bool l = true, r = true, u = true, d = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    l &= e.Ep[k] - e.dx[k] > 0;
+    r &= e.Ep[k] + e.dx[k] > 0;
+    u &= e.Ep[k] - e.dy[k] > 0;
+    d &= e.Ep[k] + e.dy[k] > 0;
+  }
+  return (l ? 1u : 0u) | (r ? 2u : 0u) | (u ? 4u : 0u) | (d ? 8u : 0u);
+}
+
 // Screen barycentrics beta_k = e_k / |D| from the exact edge values,
 // perspective-correct b_k = beta_k q_k / W with W = sum_k beta_k q_k (the
 // interpolated 1/z), using hardware reciprocals (about 1 ulp each).  Inside a
@@ -221,9 +267,7 @@ struct PixBary {
 
 __device__ __forceinline__ bool fits_i32(long long x) { return x == (long long)(int)x; }
 
-__device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
-  long long E[3];
-  edge_at(s, px, py, E);
+__device__ __forceinline__ PixBary pixel_bary_e(const Snap& s, const long long E[3]) {
   const long long Dabs = s.D < 0 ? -s.D : s.D;  // = E[0] + E[1] + E[2]
   float e[3], d;
   if (fits_i32(E[0]) && fits_i32(E[1]) && fits_i32(E[2]) && Dabs < 2147483648ll) {
@@ -250,6 +294,12 @@ __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
   o.b[2] = w[2] * iW;
   o.Wq = W;
   return o;
+}
+
+__device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
+  long long E[3];
+  edge_at(s, px, py, E);
+  return pixel_bary_e(s, E);
 }
 
 // Depth-key products at pixel (px, py) of snapped triangle s (EXACT_Q):

@@ -21,11 +21,14 @@ int launch_transform_bwd(const mer_plan* P, const mer_view* views, const mer_cam
 int launch_backface(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, float* out, hipStream_t st);
 // g: dL/d(img) rows of ld_g floats, or NULL with target != NULL for the fused
-// L2 loss (dL/d(img) = 2 w (img - target), loss += w sum (img - target)^2)
+// L2 loss (dL/d(img) = 2 w (img - target), loss += w sum (img - target)^2).
+// Scratch: tab, 2 (n_views + 1) int64 (the 16x16 tile prefix per view, written
+// here); loss_part, 4 total_btiles floats (per-wave loss partials, written
+// here; only read when loss != NULL).
 int launch_backward(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri,
                     const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
                     const float* g, const float* target, float w_l2, float* loss, int C_e, int ld_g, int flags,
-                    float* g_attr, float* g_v, void* ws, hipStream_t st);
+                    float* g_attr, float* g_v, long long* tab, float* loss_part, hipStream_t st);
 // forward-mode image tangent (flags: MER_NO_INTERSECT, MER_SKIP_EDGE, MER_SKIP_INTERP)
 int launch_jvp(const mer_plan* P, const mer_view* views, const float* v, const int32_t* tri, const int32_t* tri_id,
                const float* attr, const float* dattr, int C_a, int append_z, const float* img, int C_e,

@@ -232,3 +232,12 @@ def test_sampler_fullsize(k):
     rhs = float((torch.from_numpy(g_tex).double() * torch.from_numpy(tex).double()).sum())
     say(f"[tex] full config {k}: <G, S tex> {lhs:.6e}, <S^T G, tex> {rhs:.6e}")
     assert abs(lhs - rhs) <= 1e-4 * max(abs(lhs), 1e-30)
+    # the texture gradient over every pixel of every view, element by element
+    # against the oracle's adjoint on the same index image and uv
+    ref_gtex, ref_guv = oracle.texture_bwd(tex, uvp, g, tid)
+    check_l2(g_tex, ref_gtex, f"full config {k} g_tex (all pixels)")
+    floor = 1e-3 * float(np.abs(ref_gtex).max())
+    emax = float((np.abs(g_tex.astype(np.float64) - ref_gtex) / np.maximum(np.abs(ref_gtex), floor)).max())
+    say(f"[tex] full config {k} g_tex: max element error {emax:.2e} (floor 1e-3 max|ref|)")
+    assert emax <= 1e-3
+    check_l2(g_uv, ref_guv, f"full config {k} g_uv (all pixels)")
