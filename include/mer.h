@@ -49,6 +49,11 @@ extern "C" {
 #define MER_ETUNING (-4)    /* unsupported tile shape                        */
 #define MER_EINTERNAL (-5)  /* mer_status: an integrity check of the last
                                mer_rasterize failed (a library defect)      */
+#define MER_ESCRATCH (-6)   /* mer_backward_l2_noalloc: the plan needs more
+                               than MER_NOALLOC_SCRATCH_BYTES of scratch    */
+
+/* Size of the fixed device scratch of mer_backward_l2_noalloc. */
+#define MER_NOALLOC_SCRATCH_BYTES (8u << 20)
 
 /* edge-gradient flags */
 #define MER_NO_INTERSECT 1  /* ablation: intersection pairs scatter nothing   */
@@ -247,6 +252,26 @@ int mer_backward_l2(const mer_plan *plan, const mer_view *views_dev, const float
                     const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
                     const float *target, float weight, int C_e, int flags, float *g_attr, float *g_v, float *loss,
                     void *ws, void *stream);
+
+/* mer_backward_l2 without a workspace, for callers that cannot allocate
+ * one (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments and results as mer_backward_l2 minus
+ * `ws`; the small scratch the backward needs (the per-view tile prefix,
+ * 2 (n_views + 1) int64, and, when `loss` is not NULL, one float per wave of
+ * 64 pixels) lives in a fixed array of MER_NOALLOC_SCRATCH_BYTES bytes in
+ * the library's device memory, one per GPU, kept until the process ends.
+ * The call allocates nothing: it uses the current device's array (the
+ * stream must belong to the current device), whose address is looked up on
+ * the first call on each device.  Every call on one GPU shares that array,
+ * so calls that overlap on one GPU (different streams, no ordering) race;
+ * calls on one stream are ordered and safe.  Nothing in the array needs to
+ * start at zero: each call writes what it reads.  MER_ESCRATCH when the
+ * plan needs more scratch than the array holds (about 2 million 16x16
+ * tiles, i.e. ~500 M pixels, with `loss`; ~500 k views without). */
+int mer_backward_l2_noalloc(const mer_plan *plan, const mer_view *views_dev, const float *v, const int32_t *tri,
+                            const int32_t *tri_id, const float *attr, int C_a, int append_z, const float *img,
+                            const float *target, float weight, int C_e, int flags, float *g_attr, float *g_v,
+                            float *loss, void *stream);
 
 /* Forward mode (Sec. 5, "Forward gradients": per-pixel derivatives of the
  * image with respect to a scene parameter).  For a tangent dv of the screen

@@ -2,6 +2,7 @@
 // status.  No call allocates device memory or synchronises (mer_status aside).
 #include <limits.h>
 #include <cmath>
+#include <mutex>
 #include <string.h>
 
 #include "mer_internal.h"
@@ -30,6 +31,7 @@ const char* mer_strerror(int code) {
     case MER_ELAUNCH: return "kernel launch failed";
     case MER_ETUNING: return "unsupported tile shape";
     case MER_EINTERNAL: return "binning integrity check failed (library defect)";
+    case MER_ESCRATCH: return "the plan needs more than the fixed scratch of the no-workspace call";
     default: return "unknown error";
   }
 }
@@ -248,6 +250,57 @@ int mer_texture_bwd(const mer_plan* P, const mer_view* views_dev, const int32_t*
   if (!g_tex && !g_uv) return MER_OK;
   return mer::launch_texture_bwd(P, views_dev, tri_id, uv, ld_uv, tex, tex_h, tex_w, C_t, g_out, g_tex, g_uv, ws,
                                  (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ no-workspace backward
+// Fixed device scratch of mer_backward_l2_noalloc: every GPU the library runs
+// on holds one copy until the process ends.  In host code `scratch` only
+// names the symbol; its device address (per device) comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+constexpr size_t kScratchBytes = (size_t)MER_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch, or nullptr on failure.
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int mer_backward_l2_noalloc(const mer_plan* P, const mer_view* views_dev, const float* v, const int32_t* tri,
+                            const int32_t* tri_id, const float* attr, int C_a, int append_z, const float* img,
+                            const float* target, float weight, int C_e, int flags, float* g_attr, float* g_v,
+                            float* loss, void* stream) {
+  const int C = C_a + (append_z ? 1 : 0);
+  if (!plan_ok(P) || !views_dev || !v || !tri || !tri_id || !img || !target || C_e < 1 || C_e > 64)
+    return MER_EINVAL;
+  if (!std::isfinite(weight)) return MER_EINVAL;
+  if (!(flags & MER_SKIP_EDGE) && !g_v) return MER_EINVAL;
+  if (!(flags & MER_SKIP_INTERP) && (!attr || C_a < 1 || C_a > 64 || C > C_e)) return MER_EINVAL;
+  // the scratch holds the per-view tile prefix, then the per-wave loss partials
+  const int64_t tab_bytes = align256(2 * (int64_t)(P->n_views + 1) * 8);
+  const int64_t need = tab_bytes + (loss ? 4 * P->total_btiles * (int64_t)sizeof(float) : 0);
+  if (need > (int64_t)kScratchBytes) return MER_ESCRATCH;
+  char* base = (char*)scratch_address();
+  if (!base) return MER_ELAUNCH;
+  return mer::launch_backward(P, views_dev, v, tri, tri_id, attr, C_a, append_z ? 1 : 0, img, nullptr, target, weight,
+                              loss, C_e, C_e, flags & (MER_NO_INTERSECT | MER_SKIP_EDGE | MER_SKIP_INTERP), g_attr,
+                              g_v, (long long*)base, (float*)(base + tab_bytes), (hipStream_t)stream);
 }
 
 int mer_status(const mer_plan* P, const void* ws, void* stream, int64_t out[6]) {

@@ -21,7 +21,8 @@ SKIP_INTERP = 4
 
 SYMBOLS = ("mer_plan_init", "mer_transform", "mer_transform_bwd", "mer_rasterize", "mer_rasterize_interpolate",
            "mer_interpolate", "mer_backface", "mer_edge_grad", "mer_interpolate_bwd", "mer_backward_fused",
-           "mer_backward_l2", "mer_jvp", "mer_texture", "mer_texture_bwd", "mer_status", "mer_strerror", "mer_version")
+           "mer_backward_l2", "mer_backward_l2_noalloc", "mer_jvp", "mer_texture", "mer_texture_bwd", "mer_status",
+           "mer_strerror", "mer_version")
 
 
 class View(ctypes.Structure):
@@ -82,6 +83,8 @@ def lib():
         L.mer_backward_fused.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, i, i, P, P, P, P]
         L.mer_backward_l2.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P, P,
                                       P, P, P]
+        L.mer_backward_l2_noalloc.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, i, i, P, P, ctypes.c_float, i, i, P,
+                                              P, P, P]
         L.mer_jvp.argtypes = [ctypes.POINTER(Plan), P, P, P, P, P, P, i, i, P, i, P, i, P, P, P]
         L.mer_texture.argtypes = [ctypes.POINTER(Plan), P, P, P, i, P, i, i, i, P, P]
         L.mer_texture_bwd.argtypes = [ctypes.POINTER(Plan), P, P, P, i, P, i, i, i, P, P, P, P, P]
@@ -358,6 +361,34 @@ class Context:
                                      _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)), _ptr(img),
                                      _ptr(target), float(weight), int(img.shape[1]), int(flags), _ptr(g_attr),
                                      _ptr(g_v), _ptr(loss), _ptr(self.ws), _stream()))
+
+    def backward_l2_noalloc(self, v, tri, tri_id, attr, img, target, g_attr, g_v, weight=1.0, loss=None,
+                            append_z=False, flags=0):
+        """backward_l2 without the workspace: the call's scratch is the
+        library's fixed per-GPU array (calls that overlap on one GPU race)."""
+        import torch
+        _need(img, torch.float32, "img")
+        _need(target, torch.float32, "target")
+        _need(attr, torch.float32, "attr")
+        _need(tri_id, torch.int32, "tri_id")
+        self._geom(v, tri, attr)
+        self._px(tri_id, "tri_id")
+        self._px(img, "img")
+        self._px(target, "target", int(img.shape[1]))
+        if g_attr is not None:
+            _need(g_attr, torch.float32, "g_attr")
+            self._rows(g_attr, self.need_a, "g_attr", int(attr.shape[1]))
+        if g_v is not None:
+            _need(g_v, torch.float32, "g_v")
+            self._rows(g_v, self.need_v, "g_v", 3)
+        if loss is not None:
+            _need(loss, torch.float32, "loss")
+            if loss.numel() < 1:
+                raise MerError("loss needs one float")
+        _check(lib().mer_backward_l2_noalloc(ctypes.byref(self.plan), _ptr(self.views_dev), _ptr(v), _ptr(tri),
+                                             _ptr(tri_id), _ptr(attr), int(attr.shape[1]), int(bool(append_z)),
+                                             _ptr(img), _ptr(target), float(weight), int(img.shape[1]), int(flags),
+                                             _ptr(g_attr), _ptr(g_v), _ptr(loss), _stream()))
 
     def jvp(self, v, tri, tri_id, attr, img, dv, dimg, dattr=None, append_z=False, flags=0):
         """Forward mode: dimg [px, C_e] = image tangent for the screen-vertex

@@ -246,3 +246,17 @@ def test_peak_library_exports_what_its_header_declares():
     assert L.mer_peak_copy(None, None, 16, None) == -1
     assert L.mer_peak_atomic_add(None, 16, 256, 1, None) == -1
     assert L.mer_peak_atomic_add(ctypes.c_void_p(256), 16, 100, 1, None) == -1
+
+
+def test_noalloc_backward_checks_its_scratch_before_touching_the_device(L):
+    """mer_backward_l2_noalloc: argument errors and a plan beyond its fixed
+    scratch are refused before any device call."""
+    P = mer.plan_init(np.array([[0, 0, 0, 0, 3, 1, 32767, 32767]], np.int64))  # 4.2 M backward tiles
+    fake = ctypes.c_void_p(256)
+    args = lambda loss: (ctypes.byref(P), fake, fake, fake, fake, fake, 3, 0, fake, fake,  # noqa: E731
+                         ctypes.c_float(1.0), 3, 0, fake, fake, loss, None)
+    assert L.mer_backward_l2_noalloc(*args(fake)) == -6
+    assert b"scratch" in L.mer_strerror(-6)
+    bad = list(args(fake))
+    bad[9] = None  # no target
+    assert L.mer_backward_l2_noalloc(*bad) == -1
