@@ -393,10 +393,17 @@ def backward_roofline(s, workload, launch_ms, covered, pk):
             valu = {"valu_instr": cs["valu_instr"], "achieved": round(gi, 1), "peak": VALU_PEAK_GIPS,
                     "unit": "G wave-instr/s", "frac": round(gi / VALU_PEAK_GIPS, 4),
                     "per_wave": round(cs["valu_instr"] / cs["waves"], 1) if cs.get("waves") else None}
-        if cs.get("atomics"):
+        # the L2's atomic request counter (TCC_ATOMIC) counts requests, not
+        # lanes: the reference kernel's requests per lane-atomic convert the
+        # measured peak into requests per second
+        ref = stored_counters("reference", "k_atomic_add")
+        if cs.get("atomics") and ref and ref.get("atomics") and ref.get("lane_atomics"):
+            rpk = apk * ref["atomics"] / ref["lane_atomics"]
             atom["issued"] = cs["atomics"]
-            atom["achieved"] = round(cs["atomics"] / sec / 1e9, 2)
-            atom["frac"] = round(cs["atomics"] / sec / 1e9 / apk, 4)
+            atom["achieved"] = round(cs["atomics"] / sec / 1e9, 3)
+            atom["peak"] = round(rpk, 3)
+            atom["unit"] = "G L2 atomic requests/s"
+            atom["frac"] = round(cs["atomics"] / sec / 1e9 / rpk, 4)
             atom["pre_reduction"] = round(contrib / cs["atomics"], 2)
         traffic = cs.get("hbm_bytes")
         if cs.get("lds_bank_conflict_cycles") is not None:

@@ -32,7 +32,7 @@ DEFAULT_OUT = os.path.join(ROOT, "profiles", "counters.json")
 
 def kernel_key(name: str) -> str:
     """'void mer::k_backward<true, false, true>(...)' -> 'k_backward<true, false, true>'."""
-    n = name.split("(")[0].replace("void ", "").strip()
+    n = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").strip()
     return n.split("::")[-1] if "::" in n else n
 
 
@@ -80,6 +80,9 @@ def main(argv=None):
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--note", default="")
+    ap.add_argument("--lane-atomics", type=int, default=0,
+                    help="lane-level float atomics per dispatch of the reference kernel k_atomic_add "
+                         "(bench.py issues 256 x 8192 lanes x 32)")
     ap.add_argument("csv", nargs="+")
     a = ap.parse_args(argv)
     sys.path.insert(0, ROOT)
@@ -102,6 +105,8 @@ def main(argv=None):
     for base, k in best.items():
         wl.setdefault(base, {}).update(per[k])
         wl[base]["kernel"] = k
+        if base == "k_atomic_add" and a.lane_atomics:
+            wl[base]["lane_atomics"] = a.lane_atomics
     if a.note:
         data["note"] = a.note
     with open(a.out, "w") as f:

@@ -30,8 +30,9 @@ PK = {"copy_GBps": 5000.0, "atomic_Gops_footprint": 100.0}
 
 def test_stored_figures_follow_the_source_hash(tmp_path, monkeypatch):
     t = {"src_hash": bench.source_hash(),
-         "workloads": {"4": {"k_backward": {"valu_instr": 614400000, "waves": 1000, "atomics": 5000000,
-                                            "hbm_bytes": 12345, "lds_bank_conflict_cycles": 7, "lds_instr": 9}}}}
+         "workloads": {"4": {"k_backward": {"valu_instr": 614400000, "waves": 1000, "atomics": 500000,
+                                            "hbm_bytes": 12345, "lds_bank_conflict_cycles": 7, "lds_instr": 9}},
+                       "reference": {"k_atomic_add": {"atomics": 1000, "lane_atomics": 64000}}}}
     f = tmp_path / "counters.json"
     f.write_text(json.dumps(t))
     monkeypatch.setattr(bench, "COUNTERS_FILE", str(f))
@@ -39,8 +40,9 @@ def test_stored_figures_follow_the_source_hash(tmp_path, monkeypatch):
     # 614.4 M wave-instructions in 2 ms at 614.4 G/s peak: half the issue rate
     assert abs(r["valu"]["frac"] - 0.5) < 1e-9 and r["valu"]["per_wave"] == 614400.0
     assert r["traffic"] == 12345 and r["lds"]["bank_conflict_cycles"] == 7
-    assert r["atomic"]["contributions"] == 800 * 3 * 6 and r["atomic"]["pre_reduction"] == round(14400 / 5000000, 2)
-    assert abs(r["atomic"]["frac"] - 0.025) < 1e-9
+    assert r["atomic"]["contributions"] == 800 * 3 * 6 and r["atomic"]["pre_reduction"] == round(14400 / 500000, 2)
+    # 0.25 G requests/s against 100 G lane-atomics/s x (1000 / 64000) requests per lane-atomic
+    assert abs(r["atomic"]["frac"] - 0.25 / (100.0 / 64)) < 1e-3
     # the bound is the largest fraction
     assert r["bound"] == "alu" and r["frac"] == r["valu"]["frac"]
     assert bench.stored_counters(3, "k_backward") is None
