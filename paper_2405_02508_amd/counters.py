@@ -83,11 +83,12 @@ def main(argv=None):
     ap.add_argument("--lane-atomics", type=int, default=0,
                     help="lane-level float atomics per dispatch of the reference kernel k_atomic_add "
                          "(bench.py issues 256 x 8192 lanes x 32)")
+    ap.add_argument("--only", default="", help="keep only kernels whose name starts with this")
     ap.add_argument("csv", nargs="+")
     a = ap.parse_args(argv)
     sys.path.insert(0, ROOT)
     import bench
-    per = {k: derive(c) for k, c in read(a.csv).items()}
+    per = {k: derive(c) for k, c in read(a.csv).items() if k.startswith(a.only)}
     try:
         with open(a.out) as f:
             data = json.load(f)
