@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   if (t >= 0) S = snap_triangle<false>(v, vw, tri_row(tri, vw, t));
   if (t >= 0 && !S.ok) t = -1;
   unsigned cm = 0;  // bit d: this triangle holds neighbour d's centre
-  if (want_edge && t >= 0) cm = neighbour_cover(pix_edges(S, px, py));
+  if (want_edge && t >= 0) cm = cover_mask(S, px, py);
   s_t[lt] = t_id;
   s_cm[lt] = (unsigned char)cm;
   __syncthreads();
@@ -390,9 +390,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       continue;
     }
     if (flags & MER_NO_INTERSECT) continue;
-    // intersection: both planes' slopes along the pair's axis
+    // intersection: both planes' slopes along the pair's axis.  The asm
+    // keeps this triangle's slope here, where intersections are rare, rather
+    // than hoisted before the loop for every lane.
     const Snap Sn = snap_triangle<false>(v, vw, tri_row(tri, vw, tn));
-    const float sS = plane_slope(S, axis), sN = plane_slope(Sn, axis);
+    Snap So = S;
+    asm volatile("" : "+v"(So.z[0]), "+v"(So.z[1]), "+v"(So.z[2]), "+v"(So.X[0]), "+v"(So.X[1]), "+v"(So.X[2]),
+                 "+v"(So.Y[0]), "+v"(So.Y[1]), "+v"(So.Y[2]));
+    const float sS = plane_slope(So, axis), sN = plane_slope(Sn, axis);
     const float sA = selfA ? sS : sN, sB = selfA ? sN : sS;
     const float dlt = sB - sA;
     if (!(dlt > 0.f) || !isfinite(dlt)) continue;

@@ -185,6 +185,57 @@ __device__ __forceinline__ void edge_at(const Snap& s, int px, int py, long long
   }
 }
 
+// The same edge values in 32-bit arithmetic.  With the vertices taken
+// relative to the pixel centre, (x_k, y_k) = (X_k - Px, Y_k - Py), the
+// orientation of edge (a, b) at the centre is x_a y_b - x_b y_a.  When every
+// |x_k|, |y_k| is at most 2^14 (the triangle lies within 64 pixels of the
+// centre) each product is at most 2^28 in magnitude, so the 24-bit multiplier
+// gives it exactly, and the edge values, their sum |D| and the steps to the
+// neighbouring centres (below 2^23) fit in 32 bits: bit for bit the 64-bit
+// values.  ok is false when the bound does not hold.
+struct Rel32 {
+  int x[3], y[3];
+  bool ok;
+};
+__device__ __forceinline__ Rel32 rel32(const Snap& s, int px, int py) {
+  const unsigned Px = (unsigned)px * 256u + 128u, Py = (unsigned)py * 256u + 128u;
+  Rel32 r;
+  unsigned m = 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r.x[k] = (int)((unsigned)s.X[k] - Px);
+    r.y[k] = (int)((unsigned)s.Y[k] - Py);
+    m |= ((unsigned)r.x[k] + (1u << 14)) | ((unsigned)r.y[k] + (1u << 14));
+  }
+  r.ok = m <= (1u << 15);
+  return r;
+}
+// The 24-bit multiply as one instruction: its operands are in range here,
+// so the sign extension __mul24 would add is not needed.
+__device__ __forceinline__ int mul_i24(int a, int b) {
+  int r;
+  asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+__device__ __forceinline__ void edge32(const Snap& s, const Rel32& r, int E[3]) {
+  const bool neg = s.D < 0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int a = (k + 1) % 3, b = (k + 2) % 3;
+    const int e = mul_i24(r.x[a], r.y[b]) - mul_i24(r.x[b], r.y[a]);
+    E[k] = neg ? -e : e;
+  }
+}
+// Inward normal (A_k, B_k) of edge k and its top-left bit.
+__device__ __forceinline__ int inward_tl(const Snap& s, int k, int& A, int& B) {
+  const bool neg = s.D < 0;
+  const int a = (k + 1) % 3, b = (k + 2) % 3;
+  const int dy = s.Y[a] - s.Y[b], dx = s.X[b] - s.X[a];
+  A = neg ? -dy : dy;
+  B = neg ? -dx : dx;
+  return (A > 0 || (A == 0 && B > 0)) ? 1 : 0;
+}
+
 // Coverage rule on exact edge values: E_k > 0, or E_k == 0 on a top/left edge.
 __device__ __forceinline__ bool covered_at(const Snap& s, const long long E[3]) {
   const bool neg = s.D < 0;
@@ -203,6 +254,18 @@ __device__ __forceinline__ bool covered_at(const Snap& s, const long long E[3]) 
 // Is pixel (px, py)'s centre inside snapped triangle s by the coverage rule?
 __device__ __forceinline__ bool contains(const Snap& s, int px, int py) {
   if (!s.ok) return false;
+  const Rel32 r = rel32(s, px, py);
+  if (r.ok) {
+    int E[3];
+    edge32(s, r, E);
+    bool in = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int A, B;
+      in &= E[k] + inward_tl(s, k, A, B) > 0;
+    }
+    return in;
+  }
   long long E[3];
   edge_at(s, px, py, E);
   return covered_at(s, E);
@@ -254,6 +317,28 @@ __device__ __forceinline__ unsigned neighbour_cover(const PixEdges& e) {
   return (l ? 1u : 0u) | (r ? 2u : 0u) | (u ? 4u : 0u) | (d ? 8u : 0u);
 }
 
+// neighbour_cover(pix_edges(s, px, py)), in 32 bits where rel32 allows.
+__device__ __forceinline__ unsigned cover_mask(const Snap& s, int px, int py) {
+  const Rel32 r = rel32(s, px, py);
+  if (r.ok) {
+    int E[3];
+    edge32(s, r, E);
+    bool l = true, rt = true, u = true, d = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int A, B;
+      const int Ep = E[k] + inward_tl(s, k, A, B);
+      const int dx = A * 256, dy = B * 256;
+      l &= Ep - dx > 0;
+      rt &= Ep + dx > 0;
+      u &= Ep - dy > 0;
+      d &= Ep + dy > 0;
+    }
+    return (l ? 1u : 0u) | (rt ? 2u : 0u) | (u ? 4u : 0u) | (d ? 8u : 0u);
+  }
+  return neighbour_cover(pix_edges(s, px, py));
+}
+
 // Screen barycentrics beta_k = e_k / |D| from the exact edge values,
 // perspective-correct b_k = beta_k q_k / W with W = sum_k beta_k q_k (the
 // interpolated 1/z), using hardware reciprocals (about 1 ulp each).  Inside a
@@ -267,18 +352,7 @@ struct PixBary {
 
 __device__ __forceinline__ bool fits_i32(long long x) { return x == (long long)(int)x; }
 
-__device__ __forceinline__ PixBary pixel_bary_e(const Snap& s, const long long E[3]) {
-  const long long Dabs = s.D < 0 ? -s.D : s.D;  // = E[0] + E[1] + E[2]
-  float e[3], d;
-  if (fits_i32(E[0]) && fits_i32(E[1]) && fits_i32(E[2]) && Dabs < 2147483648ll) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) e[k] = (float)(int)E[k];
-    d = (float)(int)Dabs;
-  } else {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) e[k] = (float)E[k];
-    d = (float)Dabs;
-  }
+__device__ __forceinline__ PixBary bary_from(const Snap& s, const float e[3], float d) {
   const float id = __builtin_amdgcn_rcpf(d);
   PixBary o;
   float w[3];
@@ -296,7 +370,30 @@ __device__ __forceinline__ PixBary pixel_bary_e(const Snap& s, const long long E
   return o;
 }
 
+__device__ __forceinline__ PixBary pixel_bary_e(const Snap& s, const long long E[3]) {
+  const long long Dabs = s.D < 0 ? -s.D : s.D;  // = E[0] + E[1] + E[2]
+  float e[3], d;
+  if (fits_i32(E[0]) && fits_i32(E[1]) && fits_i32(E[2]) && Dabs < 2147483648ll) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = (float)(int)E[k];
+    d = (float)(int)Dabs;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) e[k] = (float)E[k];
+    d = (float)Dabs;
+  }
+  return bary_from(s, e, d);
+}
+
 __device__ __forceinline__ PixBary pixel_bary(const Snap& s, int px, int py) {
+  const Rel32 r = rel32(s, px, py);
+  if (r.ok) {
+    // |D| = E[0] + E[1] + E[2] < 2^31: the 32-bit conversions of pixel_bary_e
+    int E[3];
+    edge32(s, r, E);
+    const float e[3] = {(float)E[0], (float)E[1], (float)E[2]};
+    return bary_from(s, e, (float)(E[0] + E[1] + E[2]));
+  }
   long long E[3];
   edge_at(s, px, py, E);
   return pixel_bary_e(s, E);
@@ -324,13 +421,14 @@ __device__ __forceinline__ float plane_slope(const Snap& s, int axis) {
   float dq1 = q1 - q0;
   float dq2 = q2 - q0;
   float num;
+  // snapped coordinates are at most 2^28 in magnitude: differences fit 32 bits
   if (axis == 0) {
-    float a = dq1 * (float)((long long)s.Y[2] - s.Y[0]);
-    float b = dq2 * (float)((long long)s.Y[1] - s.Y[0]);
+    float a = dq1 * (float)(s.Y[2] - s.Y[0]);
+    float b = dq2 * (float)(s.Y[1] - s.Y[0]);
     num = a - b;
   } else {
-    float a = dq2 * (float)((long long)s.X[1] - s.X[0]);
-    float b = dq1 * (float)((long long)s.X[2] - s.X[0]);
+    float a = dq2 * (float)(s.X[1] - s.X[0]);
+    float b = dq1 * (float)(s.X[2] - s.X[0]);
     num = a - b;
   }
   float n256 = num * 256.0f;
