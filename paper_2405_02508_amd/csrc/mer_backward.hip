@@ -325,15 +325,28 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     if (dir == 2) return ly > 0 ? lt - 16 : 256 + 32 + lx;
     return ly < 15 ? lt + 16 : 256 + 48 + lx;
   };
+  // The pair is classified from the two masks before any image row is read:
+  // with mine = this triangle holds the neighbour's centre and theirs = the
+  // neighbour's triangle holds this centre, this side is on top when the
+  // neighbour is background (overhang), or theirs and not mine (the side
+  // whose centre the other triangle holds); both sides are when both hold
+  // (intersection).  Otherwise this side receives nothing from the pair.
   float rx = 0.f, ry = 0.f, rq = 0.f;
-  unsigned pend = 0;  // bit d: neighbour d is in the view and shows another id
+  unsigned pend = 0;  // bit d: this side receives a term from the pair with neighbour d
   if (want_edge && t >= 0) {
-    pend |= (px > 0 && s_t[nq(0)] != t) ? 1u : 0u;
-    pend |= (px + 1 < vw.W && s_t[nq(1)] != t) ? 2u : 0u;
-    pend |= (py > 0 && s_t[nq(2)] != t) ? 4u : 0u;
-    pend |= (py + 1 < vw.H && s_t[nq(3)] != t) ? 8u : 0u;
+    const bool no_isect = (flags & MER_NO_INTERSECT) != 0;
+    const bool in_view[4] = {px > 0, px + 1 < vw.W, py > 0, py + 1 < vw.H};
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int q = nq(d);  // always a slot of the tile or the ring
+      const int tn = s_t[q];
+      const bool mine = (cm >> d) & 1u;
+      const bool theirs = (s_cm[q] >> (d ^ 1)) & 1u;
+      const bool take = in_view[d] & (tn != t) & ((tn < 0) | (theirs & !(mine & no_isect)));
+      pend |= take ? 1u << d : 0u;
+    }
   }
-  // the wave takes as many rounds as its busiest lane has such neighbours
+  // the wave takes as many rounds as its busiest lane has such pairs
 #pragma unroll 1
   while (__ballot(pend != 0)) {
     if (pend == 0) continue;
@@ -370,33 +383,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       }
     }
     const float dLdp = 0.5f * acc;
-    if (tn < 0) {
-      // overhang over background: this (covered) side is on top
+    if (tn < 0 || !((cm >> dir) & 1u)) {
+      // overhang over background, or the neighbour's triangle holds this
+      // centre and this one does not hold the neighbour's: on top
       if (axis == 0) rx += dLdp;
       else ry += dLdp;
       continue;
     }
-    // mine: this triangle holds the neighbour's centre; theirs: the
-    // neighbour's triangle holds this centre (a bit of its mask)
-    const bool mine = (cm >> dir) & 1u;
-    const bool theirs = (s_cm[q] >> (dir ^ 1)) & 1u;
-    if (!mine && !theirs) continue;  // adjacent: nothing
-    if (mine != theirs) {
-      // the side whose centre the other triangle holds is on top
-      if (theirs) {
-        if (axis == 0) rx += dLdp;
-        else ry += dLdp;
-      }
-      continue;
-    }
-    if (flags & MER_NO_INTERSECT) continue;
     // intersection: both planes' slopes along the pair's axis.  The asm
     // keeps this triangle's slope here, where intersections are rare, rather
     // than hoisted before the loop for every lane.
     const Snap Sn = snap_triangle<false>(v, vw, tri_row(tri, vw, tn));
     Snap So = S;
     asm volatile("" : "+v"(So.z[0]), "+v"(So.z[1]), "+v"(So.z[2]), "+v"(So.X[0]), "+v"(So.X[1]), "+v"(So.X[2]),
-                 "+v"(So.Y[0]), "+v"(So.Y[1]), "+v"(So.Y[2]));
+                 "+v"(So.Y[0]), "+v"(So.Y[1]), "+v"(So.Y[2]), "+v"(So.D));
     const float sS = plane_slope(So, axis), sN = plane_slope(Sn, axis);
     const float sA = selfA ? sS : sN, sB = selfA ? sN : sS;
     const float dlt = sB - sA;
