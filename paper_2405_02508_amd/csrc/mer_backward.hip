@@ -136,26 +136,44 @@ __device__ __forceinline__ Snap snap_id(const float* v, const int32_t* tri, cons
 }
 
 // Segmented inclusive sum over lanes [hir, lir] of one 16-lane row of a
-// wave: four doubling steps x += m_S * x[lane - S] (S = 1, 2, 4, 8), each one
-// v_fmac_f32 whose first operand is read through a DPP row shift (a lane at
-// the start of its 16-lane row reads 0).  m_S is 1 where the lane S places to
-// the left is in the same run, else 0, so the step adds the neighbour's
-// partial sum or exactly 0.  The s_nop covers the two wait states a DPP read
-// of a register needs after a VALU write to it.
+// wave: doubling steps x += m_S * x[lane - S] (S = 1, 2, 4, 8), each a
+// v_fmac_f32 whose first operand is read through a
+// DPP row shift (a lane at the start of its 16-lane row reads 0).  m_S is 1
+// where the lane S places to the left is in the same run, else 0, so a step
+// adds the neighbour's partial sum or exactly 0.  A run of length L is summed
+// after ceil(log2 L) steps, so a wave takes only the steps its longest run of
+// covered pixels needs (steps, the same in every lane); the code that sums is
+// compiled once per step count and a wave branches once to its copy.  Each
+// step's s_nop covers the two wait states a DPP read of a register needs
+// after a VALU write to it.
 struct RunMask {
   float m1, m2, m4, m8;
+  int steps;
 };
-__device__ __forceinline__ RunMask run_mask(int lir, int hir) {
-  return {lir - 1 >= hir ? 1.f : 0.f, lir - 2 >= hir ? 1.f : 0.f, lir - 4 >= hir ? 1.f : 0.f,
-          lir - 8 >= hir ? 1.f : 0.f};
+__device__ __forceinline__ RunMask run_mask(int lir, int hir, bool covered) {
+  RunMask m = {lir - 1 >= hir ? 1.f : 0.f, lir - 2 >= hir ? 1.f : 0.f, lir - 4 >= hir ? 1.f : 0.f,
+               lir - 8 >= hir ? 1.f : 0.f, 0};
+  const int pos = lir - hir;
+  m.steps = __ballot(covered && pos >= 8) ? 4 : __ballot(covered && pos >= 4) ? 3 : __ballot(covered && pos >= 2) ? 2
+            : __ballot(covered && pos >= 1) ? 1 : 0;
+  return m;
 }
+template <int STEPS>
 __device__ __forceinline__ float seg_sum(float x, const RunMask& m) {
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m1));
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m2));
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m4));
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m8));
+  if constexpr (STEPS >= 1)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m1));
+  if constexpr (STEPS >= 2)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:2 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m2));
+  if constexpr (STEPS >= 3)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:4 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m4));
+  if constexpr (STEPS >= 4)
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %0, %1 row_shr:8 row_mask:0xf bank_mask:0xf bound_ctrl:1" : "+v"(x) : "v"(m.m8));
   return x;
 }
+template <int N>
+struct Steps {
+  static constexpr int value = N;
+};
 
 // Backward sweep over 16x16 pixel tiles of one view per workgroup (256
 // threads; wave w holds rows 4w..4w+3, 16 lanes per row).
@@ -416,7 +434,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   const int head = 63 - __clzll((long long)(F & upto));
   const bool tail = lane == 63 || ((F >> (lane + 1)) & 1ull);
   const bool emit = tail && t >= 0;
-  const RunMask rm = run_mask(lane & 15, head & 15);  // runs never cross a 16-lane row
+  const RunMask rm = run_mask(lane & 15, head & 15, t >= 0);  // runs never cross a 16-lane row
+  const bool wave_any = __ballot(t >= 0) != 0;
 
   PixBary pb;
   pb.beta[0] = pb.beta[1] = pb.beta[2] = 0.f;
@@ -431,92 +450,104 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   }
   __syncthreads();  // every slot this tile uses is claimed and zeroed
 
-  // ---- interpolation adjoint and Omega.  Both terms move vertex k's x and y
-  // by beta_k times a per-pixel vector (the fragment gradient, and minus the
-  // screen gradient of dL/d(beta) for Omega), so they are summed per pixel
-  // first; the 1/z part differs per vertex (dw).
-  float fx = rx, fy = ry;
-  float dw[3] = {0.f, 0.f, 0.f};
-  float gzc = 0.f;  // dL/d(interpolated z)
-  if (want_interp) {
-    const long long pg = t >= 0 ? p : 0;
-    const int C = C_a + append_z;
-    const int va = row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : row_vec(C_a, attr) == 3 ? 3 : 0;
-    float G[3] = {0.f, 0.f, 0.f};
-    for (int c0 = 0; c0 < C_a; c0 += 4) {  // uniform trip count: every lane joins the reductions
-      const int n = min(4, C_a - c0);
-      float4 gc4;
-      if constexpr (L2) {
-        const float4 i4 = row4(img + pg * C_e + c0, vimg, n), t4 = row4(target + pg * C_e + c0, vtar, n);
-        gc4 = make_float4((2.0f * w_l2) * (i4.x - t4.x), (2.0f * w_l2) * (i4.y - t4.y), (2.0f * w_l2) * (i4.z - t4.z),
-                          (2.0f * w_l2) * (i4.w - t4.w));
-      } else {
-        gc4 = row4(g + pg * ld_g + c0, vg, n);
-      }
-      if (t < 0) gc4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto scatter = [&](auto steps) {
+    constexpr int ST = decltype(steps)::value;
+    // ---- interpolation adjoint and Omega.  Both terms move vertex k's x and y
+    // by beta_k times a per-pixel vector (the fragment gradient, and minus the
+    // screen gradient of dL/d(beta) for Omega), so they are summed per pixel
+    // first; the 1/z part differs per vertex (dw).
+    float fx = rx, fy = ry;
+    float dw[3] = {0.f, 0.f, 0.f};
+    float gzc = 0.f;  // dL/d(interpolated z)
+    if (want_interp) {
+      const long long pg = t >= 0 ? p : 0;
+      const int C = C_a + append_z;
+      const int va = row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : row_vec(C_a, attr) == 3 ? 3 : 0;
+      float G[3] = {0.f, 0.f, 0.f};
+      for (int c0 = 0; c0 < C_a; c0 += 4) {  // uniform trip count: every lane joins the reductions
+        const int n = min(4, C_a - c0);
+        float4 gc4;
+        if constexpr (L2) {
+          const float4 i4 = row4(img + pg * C_e + c0, vimg, n), t4 = row4(target + pg * C_e + c0, vtar, n);
+          gc4 = make_float4((2.0f * w_l2) * (i4.x - t4.x), (2.0f * w_l2) * (i4.y - t4.y), (2.0f * w_l2) * (i4.z - t4.z),
+                            (2.0f * w_l2) * (i4.w - t4.w));
+        } else {
+          gc4 = row4(g + pg * ld_g + c0, vg, n);
+        }
+        if (t < 0) gc4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const float4 a4 = row4(attr + (t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0) + c0, va, n);
+        for (int k = 0; k < 3; ++k) {
+          const float4 a4 = row4(attr + (t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0) + c0, va, n);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if (j >= n) break;
-          const float gc = f4(gc4, j);
-          const int c = c0 + j;
-          G[k] += gc * f4(a4, j);
-          if (g_attr) {
-            const float sm = seg_sum(pb.b[k] * gc, rm);
-            if (emit && sm != 0.f) {
-              if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], sm);
-              else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c, sm);
+          for (int j = 0; j < 4; ++j) {
+            if (j >= n) break;
+            const float gc = f4(gc4, j);
+            const int c = c0 + j;
+            G[k] += gc * f4(a4, j);
+            if (g_attr) {
+              const float sm = seg_sum<ST>(pb.b[k] * gc, rm);
+              if (emit && sm != 0.f) {
+                if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], sm);
+                else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c, sm);
+              }
             }
           }
         }
       }
-    }
-    if (t >= 0) {
-      if (append_z) {
-        gzc = L2 ? (2.0f * w_l2) * (img[pg * C_e + C_a] - target[pg * C_e + C_a]) : g[pg * ld_g + C_a];
+      if (t >= 0) {
+        if (append_z) {
+          gzc = L2 ? (2.0f * w_l2) * (img[pg * C_e + C_a] - target[pg * C_e + C_a]) : g[pg * ld_g + C_a];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) G[k] += gzc * S.z[k];
+          for (int k = 0; k < 3; ++k) G[k] += gzc * S.z[k];
+        }
+        const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
+        const float iW = __builtin_amdgcn_rcpf(pb.Wq);
+        float dbeta[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          dw[k] = (G[k] - Gb) * iW;
+          dbeta[k] = dw[k] * S.q[k];
+        }
+        // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
+        const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const int a = (i + 1) % 3, b = (i + 2) % 3;
+          sx += dbeta[i] * ((float)(-(S.Y[b] - S.Y[a])) * invD);
+          sy += dbeta[i] * ((float)(S.X[b] - S.X[a]) * invD);
+        }
+        fx -= sx;
+        fy -= sy;
       }
-      const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
-      const float iW = __builtin_amdgcn_rcpf(pb.Wq);
-      float dbeta[3];
+      (void)C;
+    }
+    if (g_v) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        dw[k] = (G[k] - Gb) * iW;
-        dbeta[k] = dw[k] * S.q[k];
-      }
-      // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
-      const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
-      float sx = 0.f, sy = 0.f;
+        const float qk = t >= 0 ? S.q[k] : 0.f;
+        // 1/z part: the fragment's rq and Omega's dw, through d(1/z)/dz = -1/z^2;
+        // the z channel's own interpolation weight b_k
+        const float gzk = (pb.beta[k] * (rq + dw[k])) * (-(qk * qk)) + pb.b[k] * gzc;
+        const float sums[3] = {seg_sum<ST>(pb.beta[k] * fx, rm), seg_sum<ST>(pb.beta[k] * fy, rm), seg_sum<ST>(gzk, rm)};
+        if (emit) {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const int a = (i + 1) % 3, b = (i + 2) % 3;
-        sx += dbeta[i] * ((float)(-(S.Y[b] - S.Y[a])) * invD);
-        sy += dbeta[i] * ((float)(S.X[b] - S.X[a]) * invD);
-      }
-      fx -= sx;
-      fy -= sy;
-    }
-    (void)C;
-  }
-  if (g_v) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const float qk = t >= 0 ? S.q[k] : 0.f;
-      // 1/z part: the fragment's rq and Omega's dw, through d(1/z)/dz = -1/z^2;
-      // the z channel's own interpolation weight b_k
-      const float gzk = (pb.beta[k] * (rq + dw[k])) * (-(qk * qk)) + pb.b[k] * gzc;
-      const float sums[3] = {seg_sum(pb.beta[k] * fx, rm), seg_sum(pb.beta[k] * fy, rm), seg_sum(gzk, rm)};
-      if (emit) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          if (sums[j] == 0.f) continue;
-          if (slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + j], sums[j]);
-          else atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, sums[j]);
+          for (int j = 0; j < 3; ++j) {
+            if (sums[j] == 0.f) continue;
+            if (slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + j], sums[j]);
+            else atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, sums[j]);
+          }
         }
       }
+    }
+  };
+  if (wave_any) {  // a wave without a covered pixel has nothing to scatter
+    switch (rm.steps) {
+      case 0: scatter(Steps<0>{}); break;
+      case 1: scatter(Steps<1>{}); break;
+      case 2: scatter(Steps<2>{}); break;
+      case 3: scatter(Steps<3>{}); break;
+      default: scatter(Steps<4>{}); break;
     }
   }
   __syncthreads();
