@@ -55,7 +55,9 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
             ok = sn.ok;
             if (ok) {
               float a, b, n;
-              resolve_products(sn, (int)(local % vw.W), (int)(local / vw.W), a, b, n);
+              int lx, ly;
+              grid_xy(local, vw.W, lx, ly);
+              resolve_products(sn, lx, ly, a, b, n);
               const float r = __builtin_amdgcn_rcpf(n);
               b0 = a * r;
               b1 = b * r;
@@ -278,7 +280,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   const mer_view vw = views[vi];
   const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + 15) >> 4;
-  const int x0 = (int)(local_tile % tiles_x) * 16, y0 = (int)(local_tile / tiles_x) * 16;
+  int x0, y0;
+  grid_xy(local_tile, tiles_x, x0, y0);
+  x0 *= 16;
+  y0 *= 16;
   const int lane = threadIdx.x & 63;
   const int lt = threadIdx.x;  // pixel (lt & 15, lt >> 4) of the tile
   const int lx = lt & 15, ly = lt >> 4;
@@ -446,7 +451,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   int slot[3] = {-1, -1, -1};
   if (emit) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) slot[k] = slot_of(s_key, s_val, s_list, &s_nocc, S.idx[k]);
+    for (int k = 0; k < 3; ++k) {
+      const int sl = slot_of(s_key, s_val, s_list, &s_nocc, S.idx[k]);
+      slot[k] = sl >= 0 ? sl * kNV : -1;  // the slot's first value in s_val
+    }
   }
   __syncthreads();  // every slot this tile uses is claimed and zeroed
 
@@ -487,7 +495,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
             if (g_attr) {
               const float sm = seg_sum<ST>(pb.b[k] * gc, rm);
               if (emit && sm != 0.f) {
-                if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + 3 + c], sm);
+                if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] + 3 + c], sm);
                 else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c, sm);
               }
             }
@@ -534,7 +542,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
             if (sums[j] == 0.f) continue;
-            if (slot[k] >= 0) atomicAdd(&s_val[slot[k] * kNV + j], sums[j]);
+            if (slot[k] >= 0) atomicAdd(&s_val[slot[k] + j], sums[j]);
             else atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, sums[j]);
           }
         }

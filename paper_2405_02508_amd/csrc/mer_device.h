@@ -445,6 +445,15 @@ __device__ __forceinline__ long long xcd_tile(long long b, long long n) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Column and row of cell `local` of a grid `w` cells wide, in 32-bit unsigned
+// division (a view has fewer than 2^31 pixels, so fewer tiles).
+__device__ __forceinline__ void grid_xy(long long local, int w, int& x, int& y) {
+  const unsigned l = (unsigned)local, uw = (unsigned)w;
+  const unsigned q = l / uw;
+  y = (int)q;
+  x = (int)(l - q * uw);
+}
+
 // Largest i in [0, n) with base[i] <= g (base non-decreasing, base[0] <= g).
 template <typename T>
 __device__ __forceinline__ int find_bucket(const T* base, int n, long long g) {

@@ -61,7 +61,10 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
   const mer_view vw = views[vi];
   const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + TS - 1) / TS;
-  const int x0 = (int)(local_tile % tiles_x) * TS, y0 = (int)(local_tile / tiles_x) * TS;
+  int x0, y0;
+  grid_xy(local_tile, tiles_x, x0, y0);
+  x0 *= TS;
+  y0 *= TS;
   tile_tris_build<TS, true>(T, vw, x0, y0, tri_id, tri, v, dv);
 
   const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;

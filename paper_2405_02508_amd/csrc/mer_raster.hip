@@ -485,7 +485,10 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   const mer_view vw = views[vi];
   const long long local = g - tile_base[vi];
   const int tiles_x = (vw.W + TW - 1) / TW;
-  const int x0 = (int)(local % tiles_x) * TW, y0 = (int)(local / tiles_x) * TH;
+  int x0, y0;
+  grid_xy(local, tiles_x, x0, y0);
+  x0 *= TW;
+  y0 *= TH;
   const int lx = lt % TW, ly = lt / TW;
   const int px = x0 + lx, py = y0 + ly;
   const int dxs = lx * 256, dys = ly * 256;

@@ -127,8 +127,10 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
   const mer_view vw = views[vi];
   const long long local_tile = tile - btile_base[vi];
   const int tiles_x = (vw.W + 15) >> 4;
-  const int px = (int)(local_tile % tiles_x) * 16 + (threadIdx.x & 15);
-  const int py = (int)(local_tile / tiles_x) * 16 + (threadIdx.x >> 4);
+  int px, py;
+  grid_xy(local_tile, tiles_x, px, py);
+  px = px * 16 + (threadIdx.x & 15);
+  py = py * 16 + (threadIdx.x >> 4);
   const bool inside = px < vw.W && py < vw.H;
   const long long p = vw.px_off + (long long)py * vw.W + px;
   if (threadIdx.x < 4) s_box[threadIdx.x] = 0x7fffffff;
