@@ -200,21 +200,19 @@ struct Steps {
 //     (vertex, component).  Vertices that do not fit the table, and
 //     attribute channels beyond kCTab, go straight to global atomics.
 constexpr int kSlots = 256;  // vertex slots per workgroup
-constexpr int kCTab = 8;     // attribute channels reduced in LDS
+constexpr int kCTab = 8;     // attribute channels reduced in LDS (two groups of four)
 constexpr int kNV = 3 + kCTab;
 constexpr int kQ = 256 + 64;  // tile pixels and ring pixels
 
-// Find or claim the slot of vertex `key`; a new slot has its values zeroed
-// and is appended to the occupied list.  -1 when the probe limit is hit.
-__device__ __forceinline__ int slot_of(int* s_key, float* s_val, int* s_list, int* s_nocc, int key) {
+// Find or claim the slot of vertex `key`; a new slot is appended to the
+// occupied list.  -1 when the probe limit is hit.
+__device__ __forceinline__ int slot_of(int* s_key, int* s_list, int* s_nocc, int key) {
   unsigned h = ((unsigned)key * 2654435761u) >> 24;  // 8 bits
 #pragma unroll 1
   for (int probe = 0; probe < 32; ++probe) {
     const int s = (int)((h + probe) & (kSlots - 1));
     const int old = atomicCAS(&s_key[s], -1, key);
     if (old == -1) {
-#pragma unroll
-      for (int j = 0; j < kNV; ++j) s_val[s * kNV + j] = 0.f;
       s_list[atomicAdd(s_nocc, 1)] = s;
       return s;
     }
@@ -265,14 +263,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
                                                   const float* __restrict__ target, float w_l2,
                                                   float* __restrict__ loss_part) {
   __shared__ int s_key[kSlots];
-  __shared__ float s_val[kSlots * kNV];
+  __shared__ __align__(16) int s_acc[kSlots * kNV];  // fixed-point sums (the table, below)
   __shared__ int s_list[kSlots];
   __shared__ int s_nocc;
+  __shared__ __align__(16) unsigned s_mx[kSlots * 3];  // per slot and group: bits of the largest |run sum| added
   // the tile's 256 pixels, then its ring: the 64 pixels just outside it that
   // are neighbours of its border pixels (16 per side: left, right, up, down)
   __shared__ int s_t[kQ];
   __shared__ unsigned char s_cm[kQ];
+  // the table starts empty and zero: a run end may raise a slot's maximum as
+  // soon as another lane has claimed the slot
   for (int i = threadIdx.x; i < kSlots; i += blockDim.x) s_key[i] = -1;
+  for (int i = threadIdx.x; i < kSlots * kNV / 4; i += blockDim.x) reinterpret_cast<int4*>(s_acc)[i] = make_int4(0, 0, 0, 0);
+  for (int i = threadIdx.x; i < kSlots * 3 / 4; i += blockDim.x) reinterpret_cast<uint4*>(s_mx)[i] = make_uint4(0u, 0u, 0u, 0u);
   if (threadIdx.x == 0) s_nocc = 0;
 
   const long long tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -448,88 +451,129 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   pb.Wq = 1.f;
   if (t >= 0) pb = pixel_bary(S, px, py);
 
-  int slot[3] = {-1, -1, -1};
+  int slot[3] = {-1, -1, -1};  // the vertices' slots in the table
   if (emit) {
 #pragma unroll
+    for (int k = 0; k < 3; ++k) slot[k] = slot_of(s_key, s_list, &s_nocc, S.idx[k]);
+  }
+
+  auto dispatch = [&](auto&& body) {  // once per wave, with its step count as a constant
+    if (!wave_any) return;
+    switch (rm.steps) {
+      case 0: body(Steps<0>{}); break;
+      case 1: body(Steps<1>{}); break;
+      case 2: body(Steps<2>{}); break;
+      case 3: body(Steps<3>{}); break;
+      default: body(Steps<4>{}); break;
+    }
+  };
+
+  // ---- interpolation adjoint and Omega.  Both terms move vertex k's x and y
+  // by beta_k times a per-pixel vector (the fragment gradient, and minus the
+  // screen gradient of dL/d(beta) for Omega), so they are summed per pixel
+  // first; the 1/z part differs per vertex (dw).  Omega needs dL/d(b_k) =
+  // sum_c dL/d(attr_c) attr_k,c over every channel first; the run sums of
+  // b_k dL/d(attr_c) come after it, from the same (cached) rows, so that only
+  // the sums are live at the table's barrier.
+  const long long pg = t >= 0 ? p : 0;
+  const int va = row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : row_vec(C_a, attr) == 3 ? 3 : 0;
+  auto grad_row = [&](int c0, int n) -> float4 {  // dL/d(attr_c0..c0+3) of this pixel (0 for background)
+    float4 gc4;
+    if constexpr (L2) {
+      const float4 i4 = row4(img + pg * C_e + c0, vimg, n), t4 = row4(target + pg * C_e + c0, vtar, n);
+      gc4 = make_float4((2.0f * w_l2) * (i4.x - t4.x), (2.0f * w_l2) * (i4.y - t4.y), (2.0f * w_l2) * (i4.z - t4.z),
+                        (2.0f * w_l2) * (i4.w - t4.w));
+    } else {
+      gc4 = row4(g + pg * ld_g + c0, vg, n);
+    }
+    if (t < 0) gc4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    return gc4;
+  };
+  // run sums of b_k dL/d(attr_c) for channels c0..c0+3: vertex k's channel c0 + j at 4 k + j
+  // (the first chunk's row is read once, for both)
+  const float4 gc0 = want_interp && wave_any ? grad_row(0, min(4, C_a)) : make_float4(0.f, 0.f, 0.f, 0.f);
+  auto attr_sums = [&](auto steps, int c0, float(&sm)[12]) {
+    constexpr int ST = decltype(steps)::value;
+    const int n = min(4, C_a - c0);
+    const float4 gc4 = c0 == 0 ? gc0 : grad_row(c0, n);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (j >= n) break;
+        sm[4 * k + j] = seg_sum<ST>(pb.b[k] * f4(gc4, j), rm);
+      }
+  };
+  float fx = rx, fy = ry;
+  float dw[3] = {0.f, 0.f, 0.f};
+  float gzc = 0.f;  // dL/d(interpolated z)
+  if (want_interp && wave_any && t >= 0) {
+    float G[3] = {0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < C_a; c0 += 4) {
+      const int n = min(4, C_a - c0);
+      const float4 gc4 = c0 == 0 ? gc0 : grad_row(c0, n);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float4 a4 = row4(attr + (vw.a_off + S.idx[k]) * C_a + c0, va, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (j >= n) break;
+          G[k] += f4(gc4, j) * f4(a4, j);
+        }
+      }
+    }
+    if (append_z) {
+      gzc = L2 ? (2.0f * w_l2) * (img[pg * C_e + C_a] - target[pg * C_e + C_a]) : g[pg * ld_g + C_a];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) G[k] += gzc * S.z[k];
+    }
+    const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
+    const float iW = __builtin_amdgcn_rcpf(pb.Wq);
+    float dbeta[3];
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int sl = slot_of(s_key, s_val, s_list, &s_nocc, S.idx[k]);
-      slot[k] = sl >= 0 ? sl * kNV : -1;  // the slot's first value in s_val
+      dw[k] = (G[k] - Gb) * iW;
+      dbeta[k] = dw[k] * S.q[k];
+    }
+    // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
+    const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
+    float sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int a = (i + 1) % 3, b = (i + 2) % 3;
+      sx += dbeta[i] * ((float)(-(S.Y[b] - S.Y[a])) * invD);
+      sy += dbeta[i] * ((float)(S.X[b] - S.X[a]) * invD);
+    }
+    fx -= sx;
+    fy -= sy;
+  }
+  const bool attr_tab = want_interp && g_attr;
+  if (attr_tab) {
+    // channels past the table's go straight to memory
+    for (int c0 = kCTab; c0 < C_a; c0 += 4) {
+      float sm[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) sm[i] = 0.f;
+      dispatch([&](auto steps) { attr_sums(steps, c0, sm); });
+      if (emit)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (c0 + j < C_a && sm[4 * k + j] != 0.f)
+              atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c0 + j, sm[4 * k + j]);
     }
   }
-  __syncthreads();  // every slot this tile uses is claimed and zeroed
-
-  auto scatter = [&](auto steps) {
+  // the run sums the table takes: vertex k's (x, y, z) gradient at 3 k, and
+  // its channels 0-3 and 4-7 at 4 k + j
+  float sv[9], sa0[12], sa1[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    if (i < 9) sv[i] = 0.f;
+    sa0[i] = sa1[i] = 0.f;
+  }
+  dispatch([&](auto steps) {
     constexpr int ST = decltype(steps)::value;
-    // ---- interpolation adjoint and Omega.  Both terms move vertex k's x and y
-    // by beta_k times a per-pixel vector (the fragment gradient, and minus the
-    // screen gradient of dL/d(beta) for Omega), so they are summed per pixel
-    // first; the 1/z part differs per vertex (dw).
-    float fx = rx, fy = ry;
-    float dw[3] = {0.f, 0.f, 0.f};
-    float gzc = 0.f;  // dL/d(interpolated z)
-    if (want_interp) {
-      const long long pg = t >= 0 ? p : 0;
-      const int C = C_a + append_z;
-      const int va = row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : row_vec(C_a, attr) == 3 ? 3 : 0;
-      float G[3] = {0.f, 0.f, 0.f};
-      for (int c0 = 0; c0 < C_a; c0 += 4) {  // uniform trip count: every lane joins the reductions
-        const int n = min(4, C_a - c0);
-        float4 gc4;
-        if constexpr (L2) {
-          const float4 i4 = row4(img + pg * C_e + c0, vimg, n), t4 = row4(target + pg * C_e + c0, vtar, n);
-          gc4 = make_float4((2.0f * w_l2) * (i4.x - t4.x), (2.0f * w_l2) * (i4.y - t4.y), (2.0f * w_l2) * (i4.z - t4.z),
-                            (2.0f * w_l2) * (i4.w - t4.w));
-        } else {
-          gc4 = row4(g + pg * ld_g + c0, vg, n);
-        }
-        if (t < 0) gc4 = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float4 a4 = row4(attr + (t >= 0 ? (vw.a_off + S.idx[k]) * C_a : 0) + c0, va, n);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (j >= n) break;
-            const float gc = f4(gc4, j);
-            const int c = c0 + j;
-            G[k] += gc * f4(a4, j);
-            if (g_attr) {
-              const float sm = seg_sum<ST>(pb.b[k] * gc, rm);
-              if (emit && sm != 0.f) {
-                if (c < kCTab && slot[k] >= 0) atomicAdd(&s_val[slot[k] + 3 + c], sm);
-                else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + c, sm);
-              }
-            }
-          }
-        }
-      }
-      if (t >= 0) {
-        if (append_z) {
-          gzc = L2 ? (2.0f * w_l2) * (img[pg * C_e + C_a] - target[pg * C_e + C_a]) : g[pg * ld_g + C_a];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) G[k] += gzc * S.z[k];
-        }
-        const float Gb = (pb.b[0] * G[0] + pb.b[1] * G[1]) + pb.b[2] * G[2];
-        const float iW = __builtin_amdgcn_rcpf(pb.Wq);
-        float dbeta[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          dw[k] = (G[k] - Gb) * iW;
-          dbeta[k] = dw[k] * S.q[k];
-        }
-        // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
-        const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
-        float sx = 0.f, sy = 0.f;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const int a = (i + 1) % 3, b = (i + 2) % 3;
-          sx += dbeta[i] * ((float)(-(S.Y[b] - S.Y[a])) * invD);
-          sy += dbeta[i] * ((float)(S.X[b] - S.X[a]) * invD);
-        }
-        fx -= sx;
-        fy -= sy;
-      }
-      (void)C;
-    }
     if (g_v) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
@@ -537,25 +581,77 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         // 1/z part: the fragment's rq and Omega's dw, through d(1/z)/dz = -1/z^2;
         // the z channel's own interpolation weight b_k
         const float gzk = (pb.beta[k] * (rq + dw[k])) * (-(qk * qk)) + pb.b[k] * gzc;
-        const float sums[3] = {seg_sum<ST>(pb.beta[k] * fx, rm), seg_sum<ST>(pb.beta[k] * fy, rm), seg_sum<ST>(gzk, rm)};
-        if (emit) {
+        sv[3 * k] = seg_sum<ST>(pb.beta[k] * fx, rm);
+        sv[3 * k + 1] = seg_sum<ST>(pb.beta[k] * fy, rm);
+        sv[3 * k + 2] = seg_sum<ST>(gzk, rm);
+      }
+    }
+    if (attr_tab) {
+      attr_sums(steps, 0, sa0);
+      if (C_a > 4) attr_sums(steps, 4, sa1);
+    }
+  });
+
+  // ---- the vertex table, in fixed point.  A slot holds three groups of
+  // values: the coordinates (0-2) and two groups of four attribute channels
+  // (3-6, 7-10).  Every run end raises, per slot and group, the largest
+  // |run sum| it adds (an integer maximum on the float's bits); after the
+  // barrier it adds round(x 2^(22 - E)) as a 32-bit integer, with 2^E above
+  // that maximum.  At most 256 run ends add to one value, so a sum stays
+  // below 2^30; each run sum is rounded once, by at most 2^-23 of the largest
+  // one of its slot and group, and the sums are exact and independent of
+  // order.  The flush converts each back with one rounding.  A slot and group
+  // whose maximum is not finite sends its run sums straight to memory as
+  // floats, so infinities and NaNs reach the gradients as they are.
+  if (emit) {
 #pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            if (sums[j] == 0.f) continue;
-            if (slot[k] >= 0) atomicAdd(&s_val[slot[k] + j], sums[j]);
-            else atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, sums[j]);
+    for (int k = 0; k < 3; ++k) {
+      if (slot[k] < 0) continue;
+      unsigned m0 = 0u, m1 = 0u, m2 = 0u;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) m0 = max(m0, __float_as_uint(sv[3 * k + j]) & 0x7fffffffu);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        m1 = max(m1, __float_as_uint(sa0[4 * k + j]) & 0x7fffffffu);
+        m2 = max(m2, __float_as_uint(sa1[4 * k + j]) & 0x7fffffffu);
+      }
+      if (m0 != 0u) atomicMax(&s_mx[slot[k] * 3], m0);
+      if (m1 != 0u) atomicMax(&s_mx[slot[k] * 3 + 1], m1);
+      if (m2 != 0u) atomicMax(&s_mx[slot[k] * 3 + 2], m2);
+    }
+  }
+  __syncthreads();  // every slot is claimed and zeroed, and its maxima are final
+  if (emit) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int sk = slot[k];
+#pragma unroll
+      for (int grp = 0; grp < 3; ++grp) {
+        if (grp == 0 ? !g_v : !attr_tab) continue;
+        int sh = 0;
+        bool fixed = false;
+        if (sk >= 0) {
+          const unsigned M = s_mx[sk * 3 + grp];
+          fixed = M < 0x7f800000u;
+          int E = 0;
+          (void)frexpf(__uint_as_float(M), &E);
+          sh = 22 - E;
+        }
+#pragma unroll
+        for (int j = 0; j < (grp == 0 ? 3 : 4); ++j) {
+          const float x = grp == 0 ? sv[3 * k + j] : grp == 1 ? sa0[4 * k + j] : sa1[4 * k + j];
+          const int col = grp == 0 ? j : 3 + 4 * (grp - 1) + j;  // value in the slot; channel col - 3
+          if (x == 0.f || (grp > 0 && col - 3 >= C_a)) continue;
+          if (fixed) {
+            const int qv = (int)rintf(ldexpf(x, sh));
+            if (qv != 0) atomicAdd(&s_acc[__umul24(sk, kNV) + col], qv);
+          } else if (grp == 0) {
+            atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, x);
+          } else {
+            atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + col - 3, x);
           }
         }
       }
-    }
-  };
-  if (wave_any) {  // a wave without a covered pixel has nothing to scatter
-    switch (rm.steps) {
-      case 0: scatter(Steps<0>{}); break;
-      case 1: scatter(Steps<1>{}); break;
-      case 2: scatter(Steps<2>{}); break;
-      case 3: scatter(Steps<3>{}); break;
-      default: scatter(Steps<4>{}); break;
     }
   }
   __syncthreads();
@@ -567,8 +663,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
     const int s = s_list[i];
     const int key = s_key[s];
     for (int j = threadIdx.x & 15; j < nv; j += 16) {
-      const float x = s_val[s * kNV + j];
-      if (x == 0.f) continue;
+      const int qv = s_acc[s * kNV + j];
+      if (qv == 0) continue;
+      int E = 0;
+      (void)frexpf(__uint_as_float(s_mx[s * 3 + (j < 3 ? 0 : j < 7 ? 1 : 2)]), &E);
+      const float x = ldexpf((float)qv, E - 22);
       if (j < 3) {
         if (g_v) atomicAdd(g_v + (vw.v_off + key) * 3 + j, x);
       } else if (g_attr) {
