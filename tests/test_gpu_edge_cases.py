@@ -195,3 +195,33 @@ def test_forward_mode_and_texture_on_empty_and_extreme_views():
     s = _scene([(np.zeros((0, 3)), np.zeros((0, 3)), 9, 13), (v, t, 20, 24), (vd, td, 10, 18),
                 (v1, t1, 1, 37), (v2, t2, 37, 1), (v3, t3, 1, 1)])
     _jvp_and_texture(s, 3)
+
+
+def test_nonfinite_image_gradient_is_not_dropped():
+    """A NaN and an infinity in dL/d(image) at covered pixels of different
+    tiles: every vertex gradient the oracle makes non-finite is non-finite on
+    the GPU too (the vertex table hands such sums to memory as floats), and
+    the GPU values that stay finite match the oracle's.  The GPU may mark more
+    entries: its run sums multiply a neighbouring run's value by 0, and
+    0 * inf is NaN, so a non-finite value can reach the runs next to it in its
+    16-pixel row."""
+    s = scenes.make_config(1)
+    g = scenes.image_grad(s, 5)
+    f = oracle.forward(s)
+    cov = np.flatnonzero(f["tri_id"] >= 0)
+    W = s.view(0)["W"]
+    p_nan = int(cov[len(cov) // 4])
+    far = cov[np.abs(cov // W - p_nan // W) > 20]  # another tile row
+    p_inf = int(far[len(far) // 2])
+    g[p_nan, :] = np.nan
+    g[p_inf, 0] = np.inf
+    say(f"[edge] non-finite dL/dI at pixels {p_nan}, {p_inf}")
+    ref = run_oracle(s, g)
+    got = run_gpu(s, g)
+    for name in ("g_v", "g_attr"):
+        rf, gf = np.isfinite(ref[name]), np.isfinite(got[name])
+        assert (~rf).any(), f"{name}: the oracle should see the non-finite inputs"
+        assert not np.any(~rf & gf), f"{name}: a non-finite contribution was dropped"
+        both = rf & gf
+        a, b = got[name][both].astype(np.float64), ref[name][both]
+        assert np.abs(a - b).max() <= 1e-5 * max(1.0, np.abs(b).max()), name
