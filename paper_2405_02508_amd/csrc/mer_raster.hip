@@ -479,6 +479,9 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    int C_a, int append_z, float* __restrict__ out) {
   constexpr int NT = TW * TH;
   __shared__ TileRec s_tr[NT];
+  // single-wave tiles: the chunk's records go to s_tr nearest first
+  constexpr bool kSort = NT == 64;
+  __shared__ float s_qs[kSort ? NT : 1];
   const long long g = xcd_tile(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
@@ -559,14 +562,31 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         o.t = (int)(r - tb);
         o.tneg = 0xFFFFFFFFu - (unsigned)o.t;
       }
-      s_tr[lt] = o;
+      if constexpr (kSort) s_qs[lt] = o.t >= 0 ? o.qb : -1.0f;
+      else s_tr[lt] = o;
+      if constexpr (kSort) {
+        // The winner is the largest key whatever the order, so the chunk is
+        // taken nearest first: record i goes to its rank by early-z bound qb
+        // (descending, ties by index, skipped records last).  Once no lane's
+        // surface is as far as a record's bound, no later record can win.
+        __builtin_amdgcn_wave_barrier();
+        const float mq = s_qs[lt];
+        int rank = 0;
+        for (int i = 0; i < n; ++i) {
+          const float oq = s_qs[i];
+          rank += (oq > mq) | ((oq == mq) & (i < lt));
+        }
+        s_tr[rank] = o;
+      }
     }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
       const TileRec T = s_tr[j];  // five 16-byte LDS broadcasts
       const int t = T.t;
+      if (kSort && t < 0) break;  // sorted: only skipped records follow
       if (t < 0) continue;  // uniform across the block
       const float best_q = key_q(best);
+      if (kSort && !__ballot(inside && T.qb >= best_q)) break;  // nor can any record after it
       if (T.fast) {
         // 32-bit path: covered iff off_k > thr_k for all k; then the unbiased
         // edge values are u0_k + off_k exactly (mod 2^32 and in [0, 2^31))
