@@ -603,18 +603,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   // order.  The flush converts each back with one rounding.  A slot and group
   // whose maximum is not finite sends its run sums straight to memory as
   // floats, so infinities and NaNs reach the gradients as they are.
+  const bool grp2 = attr_tab && C_a > 4;  // the second attribute group is in use
+  unsigned nz = 0u;  // bit 3 k + grp: this run end has a nonzero sum in vertex k's group grp
   if (emit) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      if (slot[k] < 0) continue;
       unsigned m0 = 0u, m1 = 0u, m2 = 0u;
+      if (g_v)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) m0 = max(m0, __float_as_uint(sv[3 * k + j]) & 0x7fffffffu);
+        for (int j = 0; j < 3; ++j) m0 = max(m0, __float_as_uint(sv[3 * k + j]) & 0x7fffffffu);
+      if (attr_tab)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        m1 = max(m1, __float_as_uint(sa0[4 * k + j]) & 0x7fffffffu);
-        m2 = max(m2, __float_as_uint(sa1[4 * k + j]) & 0x7fffffffu);
-      }
+        for (int j = 0; j < 4; ++j) m1 = max(m1, __float_as_uint(sa0[4 * k + j]) & 0x7fffffffu);
+      if (grp2)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) m2 = max(m2, __float_as_uint(sa1[4 * k + j]) & 0x7fffffffu);
+      nz |= (m0 != 0u ? 1u : 0u) << (3 * k) | (m1 != 0u ? 2u : 0u) << (3 * k) | (m2 != 0u ? 4u : 0u) << (3 * k);
+      if (slot[k] < 0) continue;
       if (m0 != 0u) atomicMax(&s_mx[slot[k] * 3], m0);
       if (m1 != 0u) atomicMax(&s_mx[slot[k] * 3 + 1], m1);
       if (m2 != 0u) atomicMax(&s_mx[slot[k] * 3 + 2], m2);
@@ -627,7 +632,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       const int sk = slot[k];
 #pragma unroll
       for (int grp = 0; grp < 3; ++grp) {
-        if (grp == 0 ? !g_v : !attr_tab) continue;
+        if (!((nz >> (3 * k + grp)) & 1u)) continue;
         int sh = 0;
         bool fixed = false;
         if (sk >= 0) {
