@@ -24,7 +24,8 @@ struct __align__(16) Rec {
   int A[3];
   int B[3];
   float q[3];  // 1/z of the three vertices, binary32
-  int tl;      // bit k: edge k is a top or left edge
+  int tl;      // bit k < 3: edge k is a top or left edge; bit 3: the 32-bit raster path
+               // applies; bit 4: bits 16-31 hold the binning pass's tile mask
 };
 static_assert(sizeof(Rec) == 64, "record layout");
 

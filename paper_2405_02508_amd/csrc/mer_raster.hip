@@ -117,6 +117,25 @@ __device__ __forceinline__ void wave_each_tile(const Rec& R, const BBox& bb, int
     box_tile_test(R, bb, tiles_x, base, tw_log2, th_log2, tx0 + k % ntx, ty0 + k / ntx, f);
 }
 
+// Tiles of a box of at most 16 tiles whose test passed, as a 16-bit mask
+// over the box's tiles in row-major order (the count pass stores it in bits
+// 16-31 of the record's tl word, with bit 4 set): the fill pass walks the
+// set bits instead of testing every tile again.
+constexpr int kMaskValid = 16;
+template <typename F>
+__device__ __forceinline__ void for_each_masked_tile(unsigned m, const BBox& bb, int W, long long base, int tw_log2,
+                                                     int th_log2, F f) {
+  const int tiles_x = (W + (1 << tw_log2) - 1) >> tw_log2;
+  const int tx0 = bb.x0 >> tw_log2, ty0 = bb.y0 >> th_log2, ntx = (bb.x1 >> tw_log2) - tx0 + 1;
+  const unsigned inv = (256u + (unsigned)ntx - 1u) / (unsigned)ntx;  // k / ntx = (k inv) >> 8 for k < 16, ntx <= 16
+  while (m) {
+    const int k = __builtin_ctz(m);
+    m &= m - 1u;
+    const int dy = (int)(((unsigned)k * inv) >> 8), dx = k - dy * ntx;
+    f((int)(base + (long long)(ty0 + dy) * tiles_x + tx0 + dx));
+  }
+}
+
 // Workgroup table of tile counters: the count and fill passes add into LDS
 // and touch each tile's global counter once per workgroup (a workgroup of
 // large triangles can meet thousands of tiles; tiles the table does not take
@@ -226,20 +245,30 @@ __global__ void __launch_bounds__(kBinBlock) k_setup(const mer_view* __restrict_
           }
         }
       } else if (pxa <= pxb && pya <= pyb) {
-        rec[g] = R;
+        Rec Rm = R;
         bb.x0 = (short)pxa;
         bb.x1 = (short)pxb;
         bb.y0 = (short)pya;
         bb.y1 = (short)pyb;
-        if (box_tiles(bb, tw_log2, th_log2) > big_tiles) {
+        const int nb = box_tiles(bb, tw_log2, th_log2);
+        if (nb > big_tiles) {
           s_big[atomicAdd(&s_nbig, 1)] = (int)g;  // counted by k_bin_big
         } else {
-          for_each_tile(R, bb, vw.W, tile_base[vi], tw_log2, th_log2, [&](int gt) {
-            const int sl = tile_slot<true, true>(s_tkey, &s_nocc, gt);
-            if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
-            else atomicAdd(count + gt, 1);
-          });
+          const int tiles_x = (vw.W + (1 << tw_log2) - 1) >> tw_log2;
+          const long long base = tile_base[vi];
+          unsigned mask = 0u;
+          int k = 0;
+          for (int ty = bb.y0 >> th_log2; ty <= (bb.y1 >> th_log2); ++ty)
+            for (int tx = bb.x0 >> tw_log2; tx <= (bb.x1 >> tw_log2); ++tx, ++k)
+              box_tile_test(R, bb, tiles_x, base, tw_log2, th_log2, tx, ty, [&](int gt) {
+                mask |= k < 16 ? 1u << k : 0u;
+                const int sl = tile_slot<true, true>(s_tkey, &s_nocc, gt);
+                if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
+                else atomicAdd(count + gt, 1);
+              });
+          if (nb <= 16) Rm.tl |= kMaskValid | (int)(mask << 16);
         }
+        rec[g] = Rm;
       }
     }
     bbox[g] = bb;
@@ -364,14 +393,26 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
   if (g < total_tris) bb = bbox[g];
   const bool live = bb.x0 <= bb.x1 && box_tiles(bb, tw_log2, th_log2) <= big_tiles;  // large ones: k_bin_big
   Rec R;
+  R.tl = 0;
   int W = 0;
   long long base = 0;
+  // the count pass's masks when every triangle of the wave has one (one
+  // walk for the whole wave), else the same tests again
+  bool masked = false;
+  auto each_tile = [&](auto f) {
+    if (masked) for_each_masked_tile((unsigned)R.tl >> 16, bb, W, base, tw_log2, th_log2, f);
+    else for_each_tile(R, bb, W, base, tw_log2, th_log2, f);
+  };
   if (live) {
     const int vi = wave_bucket(tri_base, n_views, g);
     W = views[vi].W;
     base = tile_base[vi];
-    R = rec[g];
-    for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
+    R.tl = rec[g].tl;
+  }
+  masked = __ballot(live && !(R.tl & kMaskValid)) == 0ull;
+  if (live && !masked) R = rec[g];  // the whole record only for the tests
+  if (live) {
+    each_tile([&](int gt) {
       const int sl = tile_slot<true, false>(s_tkey, &s_nocc, gt);
       if (sl >= 0) atomicAdd(&s_tcnt[sl], 1);
     });
@@ -389,7 +430,7 @@ __global__ void __launch_bounds__(kBinBlock) k_fill(const mer_view* __restrict__
   // the table is frozen: a tile in it takes the next position of the
   // workgroup's range, any other tile its own global counter
   if (live) {
-    for_each_tile(R, bb, W, base, tw_log2, th_log2, [&](int gt) {
+    each_tile([&](int gt) {
       const int sl = tile_slot<false, false>(s_tkey, &s_nocc, gt);
       const long long pos = sl >= 0 ? (long long)s_toff[sl] + atomicAdd(&s_tcnt[sl], 1)
                                     : (long long)offs[gt] + (atomicSub(count + gt, 1) - 1);
