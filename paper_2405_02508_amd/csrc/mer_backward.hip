@@ -642,18 +642,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
           (void)frexpf(__uint_as_float(M), &E);
           sh = 22 - E;
         }
+        const int col0 = grp == 0 ? 0 : 3 + 4 * (grp - 1);  // the group's first value in the slot
+        if (fixed) {
+          // every value of the group, zeros included: an integer LDS add
+          // costs about the same for any number of active lanes, a branch
+          // per value does not (columns past C_a hold zeros and are never
+          // flushed)
+          int* acc = &s_acc[__umul24(sk, kNV) + col0];
 #pragma unroll
-        for (int j = 0; j < (grp == 0 ? 3 : 4); ++j) {
-          const float x = grp == 0 ? sv[3 * k + j] : grp == 1 ? sa0[4 * k + j] : sa1[4 * k + j];
-          const int col = grp == 0 ? j : 3 + 4 * (grp - 1) + j;  // value in the slot; channel col - 3
-          if (x == 0.f || (grp > 0 && col - 3 >= C_a)) continue;
-          if (fixed) {
-            const int qv = (int)rintf(ldexpf(x, sh));
-            if (qv != 0) atomicAdd(&s_acc[__umul24(sk, kNV) + col], qv);
-          } else if (grp == 0) {
-            atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, x);
-          } else {
-            atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + col - 3, x);
+          for (int j = 0; j < (grp == 0 ? 3 : 4); ++j) {
+            const float x = grp == 0 ? sv[3 * k + j] : grp == 1 ? sa0[4 * k + j] : sa1[4 * k + j];
+            atomicAdd(acc + j, (int)rintf(ldexpf(x, sh)));
+          }
+        } else {
+#pragma unroll
+          for (int j = 0; j < (grp == 0 ? 3 : 4); ++j) {
+            const float x = grp == 0 ? sv[3 * k + j] : grp == 1 ? sa0[4 * k + j] : sa1[4 * k + j];
+            if (x == 0.f || (grp > 0 && col0 + j - 3 >= C_a)) continue;
+            if (grp == 0) atomicAdd(g_v + (vw.v_off + S.idx[k]) * 3 + j, x);
+            else atomicAdd(g_attr + (vw.a_off + S.idx[k]) * C_a + col0 + j - 3, x);
           }
         }
       }
