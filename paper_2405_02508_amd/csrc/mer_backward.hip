@@ -620,9 +620,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
         for (int j = 0; j < 4; ++j) m2 = max(m2, __float_as_uint(sa1[4 * k + j]) & 0x7fffffffu);
       nz |= (m0 != 0u ? 1u : 0u) << (3 * k) | (m1 != 0u ? 2u : 0u) << (3 * k) | (m2 != 0u ? 4u : 0u) << (3 * k);
       if (slot[k] < 0) continue;
-      if (m0 != 0u) atomicMax(&s_mx[slot[k] * 3], m0);
-      if (m1 != 0u) atomicMax(&s_mx[slot[k] * 3 + 1], m1);
-      if (m2 != 0u) atomicMax(&s_mx[slot[k] * 3 + 2], m2);
+      // a maximum with 0 changes nothing: no branch per group
+      unsigned* mx = &s_mx[__umul24(slot[k], 3)];
+      if (g_v) atomicMax(mx, m0);
+      if (attr_tab) atomicMax(mx + 1, m1);
+      if (grp2) atomicMax(mx + 2, m2);
     }
   }
   __syncthreads();  // every slot is claimed and zeroed, and its maxima are final
