@@ -604,7 +604,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   // whose maximum is not finite sends its run sums straight to memory as
   // floats, so infinities and NaNs reach the gradients as they are.
   const bool grp2 = attr_tab && C_a > 4;  // the second attribute group is in use
-  unsigned nz = 0u;  // bit 3 k + grp: this run end has a nonzero sum in vertex k's group grp
   if (emit) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -618,7 +617,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       if (grp2)
 #pragma unroll
         for (int j = 0; j < 4; ++j) m2 = max(m2, __float_as_uint(sa1[4 * k + j]) & 0x7fffffffu);
-      nz |= (m0 != 0u ? 1u : 0u) << (3 * k) | (m1 != 0u ? 2u : 0u) << (3 * k) | (m2 != 0u ? 4u : 0u) << (3 * k);
       if (slot[k] < 0) continue;
       // a maximum with 0 changes nothing: no branch per group
       unsigned* mx = &s_mx[__umul24(slot[k], 3)];
@@ -634,7 +632,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       const int sk = slot[k];
 #pragma unroll
       for (int grp = 0; grp < 3; ++grp) {
-        if (!((nz >> (3 * k + grp)) & 1u)) continue;
+        if (grp == 0 ? !g_v : grp == 1 ? !attr_tab : !grp2) continue;  // groups not in use
         int sh = 0;
         bool fixed = false;
         if (sk >= 0) {
