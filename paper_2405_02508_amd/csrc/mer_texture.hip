@@ -231,26 +231,32 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
   const int sh = 52 - e;
   for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) s_acc[i] = 0ull;
   __syncthreads();
+  // channel-major window (value c of texel i at c * ncell + i): the lanes of
+  // a wave touch neighbouring texels, which then sit 8 bytes apart in LDS
+  // rather than C * 8 bytes (with C = 8, four banks for the whole wave)
+  const int ncell = (int)(bw * bh);
   if (cell.ok) {
-    const int l00 = (int)(((cell.y[0] - by0) * bw + (cell.x[0] - bx0)) * C);
-    const int l10 = (int)(((cell.y[0] - by0) * bw + (cell.x[1] - bx0)) * C);
-    const int l01 = (int)(((cell.y[1] - by0) * bw + (cell.x[0] - bx0)) * C);
-    const int l11 = (int)(((cell.y[1] - by0) * bw + (cell.x[1] - bx0)) * C);
+    const int l00 = (int)((cell.y[0] - by0) * bw + (cell.x[0] - bx0));
+    const int l10 = (int)((cell.y[0] - by0) * bw + (cell.x[1] - bx0));
+    const int l01 = (int)((cell.y[1] - by0) * bw + (cell.x[0] - bx0));
+    const int l11 = (int)((cell.y[1] - by0) * bw + (cell.x[1] - bx0));
     for (int c = 0; c < C; ++c) {
       const float gc = g[c];
       if (gc == 0.f) continue;
+      unsigned long long* a = s_acc + c * ncell;
       // |w g 2^sh| < 2^52: exact in binary64, rounded to the nearest integer
-      atomicAdd(&s_acc[l00 + c], (unsigned long long)(long long)rint(ldexp((double)(w00 * gc), sh)));
-      atomicAdd(&s_acc[l10 + c], (unsigned long long)(long long)rint(ldexp((double)(w10 * gc), sh)));
-      atomicAdd(&s_acc[l01 + c], (unsigned long long)(long long)rint(ldexp((double)(w01 * gc), sh)));
-      atomicAdd(&s_acc[l11 + c], (unsigned long long)(long long)rint(ldexp((double)(w11 * gc), sh)));
+      atomicAdd(a + l00, (unsigned long long)(long long)rint(ldexp((double)(w00 * gc), sh)));
+      atomicAdd(a + l10, (unsigned long long)(long long)rint(ldexp((double)(w10 * gc), sh)));
+      atomicAdd(a + l01, (unsigned long long)(long long)rint(ldexp((double)(w01 * gc), sh)));
+      atomicAdd(a + l11, (unsigned long long)(long long)rint(ldexp((double)(w11 * gc), sh)));
     }
   }
   __syncthreads();
+  // the flush walks texel-major, so a wave's global atomics stay contiguous
   for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) {
-    const long long q = (long long)s_acc[i];
-    if (q == 0) continue;
     const int c = i % C, cell_i = i / C;
+    const long long q = (long long)s_acc[c * ncell + cell_i];
+    if (q == 0) continue;
     const long long ty = by0 + cell_i / bw, tx = bx0 + cell_i % bw;
     atomicAdd(g_tex + (ty * tw + tx) * C + c, (float)ldexp((double)q, -sh));
   }
