@@ -449,6 +449,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   pb.beta[0] = pb.beta[1] = pb.beta[2] = 0.f;
   pb.b[0] = pb.b[1] = pb.b[2] = 0.f;
   pb.Wq = 1.f;
+  pb.d = 1.f;
   if (t >= 0) pb = pixel_bary(S, px, py);
 
   int slot[3] = {-1, -1, -1};  // the vertices' slots in the table
@@ -536,7 +537,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       dbeta[k] = dw[k] * S.q[k];
     }
     // d beta_i / d v_j = -beta_j * grad_P beta_i;  grad_P beta_i = 256 (-(Yb-Ya), Xb-Xa) / D
-    const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
+    const float invD = 256.0f * __builtin_amdgcn_rcpf(S.D < 0 ? -pb.d : pb.d);  // (float)D, already converted
     float sx = 0.f, sy = 0.f;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {

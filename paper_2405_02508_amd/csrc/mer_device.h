@@ -349,6 +349,7 @@ struct PixBary {
   float beta[3];
   float b[3];
   float Wq;
+  float d;  // (float)|D|
 };
 
 __device__ __forceinline__ bool fits_i32(long long x) { return x == (long long)(int)x; }
@@ -368,6 +369,7 @@ __device__ __forceinline__ PixBary bary_from(const Snap& s, const float e[3], fl
   o.b[1] = w[1] * iW;
   o.b[2] = w[2] * iW;
   o.Wq = W;
+  o.d = d;
   return o;
 }
 

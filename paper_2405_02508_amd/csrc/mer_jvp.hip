@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
         ex += pb.beta[j] * T.dv[3 * j][t];
         ey += pb.beta[j] * T.dv[3 * j + 1][t];
       }
-      const float invD = 256.0f * __builtin_amdgcn_rcpf((float)S.D);
+      const float invD = 256.0f * __builtin_amdgcn_rcpf(S.D < 0 ? -pb.d : pb.d);  // (float)D, already converted
       float dw[3];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
