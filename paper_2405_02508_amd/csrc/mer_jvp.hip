@@ -14,6 +14,15 @@ namespace mer {
 
 // Screen barycentrics e_k / |D| at pixel (px, py) of snapped triangle s.
 __device__ __forceinline__ void screen_beta(const Snap& s, int px, int py, float beta[3]) {
+  const Rel32 r = rel32(s, px, py);
+  if (r.ok) {  // the same values from 32-bit edge values (|D| = their sum)
+    int E[3];
+    edge32(s, r, E);
+    const float id = __builtin_amdgcn_rcpf((float)(E[0] + E[1] + E[2]));
+#pragma unroll
+    for (int k = 0; k < 3; ++k) beta[k] = (float)E[k] * id;
+    return;
+  }
   long long E[3];
   edge_at(s, px, py, E);
   const long long Dabs = s.D < 0 ? -s.D : s.D;
