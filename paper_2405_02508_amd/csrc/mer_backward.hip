@@ -160,6 +160,14 @@ __device__ __forceinline__ RunMask run_mask(int lir, int hir, bool covered) {
             : __ballot(covered && pos >= 1) ? 1 : 0;
   return m;
 }
+// Nearest integer of x (halves rounded up) in one instruction: floor(x + 0.5),
+// exact for |x| < 2^22 (x + 0.5 is then representable).
+__device__ __forceinline__ int round_half_up(float x) {
+  int q;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(q) : "v"(x));
+  return q;
+}
+
 template <int STEPS>
 __device__ __forceinline__ float seg_sum(float x, const RunMask& m) {
   if constexpr (STEPS >= 1)
@@ -653,7 +661,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
 #pragma unroll
           for (int j = 0; j < (grp == 0 ? 3 : 4); ++j) {
             const float x = grp == 0 ? sv[3 * k + j] : grp == 1 ? sa0[4 * k + j] : sa1[4 * k + j];
-            atomicAdd(acc + j, (int)rintf(ldexpf(x, sh)));
+            atomicAdd(acc + j, round_half_up(ldexpf(x, sh)));
           }
         } else {
 #pragma unroll
