@@ -229,34 +229,6 @@ __device__ __forceinline__ int slot_of(int* s_key, int* s_list, int* s_nocc, int
   return -1;
 }
 
-// Up to four consecutive floats of a row, with one vector load where the
-// channel count allows it (vec: 4 = rows of a multiple of 4 floats at a
-// 16-byte aligned base, 3 = rows of 3 floats, 0 = one load per float).
-__device__ __forceinline__ float4 row4(const float* __restrict__ a, int vec, int n) {
-  if (vec == 4) return *reinterpret_cast<const float4*>(a);
-  if (vec == 3) {
-    const float3 x = *reinterpret_cast<const float3*>(a);
-    return make_float4(x.x, x.y, x.z, 0.f);
-  }
-  float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-  x.x = a[0];
-  if (n > 1) x.y = a[1];
-  if (n > 2) x.z = a[2];
-  if (n > 3) x.w = a[3];
-  return x;
-}
-__device__ __forceinline__ int row_vec(int C, const void* base) {
-  return C == 3 ? 3 : ((C & 3) == 0 && ((uintptr_t)base & 15) == 0) ? 4 : 0;
-}
-__device__ __forceinline__ float f4(const float4& x, int j) { return j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w; }
-// Two consecutive floats of a row, one 8-byte load when vec2 (rows of an
-// even number of floats at an 8-byte aligned base), else two loads (the
-// second only when n > 1).
-__device__ __forceinline__ float2 row2(const float* __restrict__ a, bool vec2, int n) {
-  if (vec2) return *reinterpret_cast<const float2*>(a);
-  return make_float2(a[0], n > 1 ? a[1] : 0.f);
-}
-
 // L2: dL/d(img) = 2 w (img - target) is formed here instead of read from g.
 // LOSS: w * sum (img - target)^2 over each wave's 64 pixels goes to
 // loss_part[4 tile + wave] (computed last, when few registers are live).

@@ -202,27 +202,75 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
 #pragma unroll
     for (int k = 0; k < 3; ++k) arow[k] = (vw.a_off + S.idx[k]) * C_a;
   }
+  // four channels at a time, rows as vector loads where the channel counts
+  // allow (image rows of C_e floats, attribute and tangent rows of C_a);
+  // each channel's arithmetic is the same, in the same order, as one at a time
+  const int vimg = img ? row_vec(C_e, img) : 0;
+  const bool a_al = ((vw.a_off * C_a) & 3) == 0;
+  const int va = row_vec(C_a, attr) == 3 ? 3 : row_vec(C_a, attr) == 4 && a_al ? 4 : 0;
+  const int vda = !dattr ? 0 : row_vec(C_a, dattr) == 3 ? 3 : row_vec(C_a, dattr) == 4 && a_al ? 4 : 0;
+  const int vout = row_vec(C_e, dimg);
   float* out = dimg + p * C_e;
-  for (int c = 0; c < C_e; ++c) {
-    float x = 0.f;
-    if (interior && c < C_out) {
-      if (c < C_a) {
-        x = (db[0] * attr[arow[0] + c] + db[1] * attr[arow[1] + c]) + db[2] * attr[arow[2] + c];
-        if (dattr) x += (b[0] * dattr[arow[0] + c] + b[1] * dattr[arow[1] + c]) + b[2] * dattr[arow[2] + c];
-      } else {
-        x = zt;
+  for (int c0 = 0; c0 < C_e; c0 += 4) {
+    const int n = min(4, C_e - c0);
+    float xs[4] = {0.f, 0.f, 0.f, 0.f};
+    if (interior && c0 < C_out) {
+      if (c0 < C_a) {
+        const int na = min(4, C_a - c0);
+        const float4 a0 = row4(attr + arow[0] + c0, va, na), a1 = row4(attr + arow[1] + c0, va, na),
+                     a2 = row4(attr + arow[2] + c0, va, na);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (j < na) xs[j] = (db[0] * f4(a0, j) + db[1] * f4(a1, j)) + db[2] * f4(a2, j);
+        if (dattr) {
+          const float4 e0 = row4(dattr + arow[0] + c0, vda, na), e1 = row4(dattr + arow[1] + c0, vda, na),
+                       e2 = row4(dattr + arow[2] + c0, vda, na);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < na) xs[j] += (b[0] * f4(e0, j) + b[1] * f4(e1, j)) + b[2] * f4(e2, j);
+        }
+      }
+      if (C_out > C_a && C_a >= c0 && C_a < c0 + n) {  // the z channel
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (c0 + j == C_a) xs[j] = zt;
       }
     }
     if (has_edge) {
-      const float s0 = i0[c];
-      float e = 0.f;
-      if (d4[0] != 0.f) e += (i0[c - C_e] - s0) * d4[0];
-      if (d4[1] != 0.f) e += (s0 - i0[c + C_e]) * d4[1];
-      if (d4[2] != 0.f) e += (i0[c - W * C_e] - s0) * d4[2];
-      if (d4[3] != 0.f) e += (s0 - i0[c + W * C_e]) * d4[3];
-      x += 0.5f * e;
+      const float4 s0 = row4(i0 + c0, vimg, n);
+      float e[4] = {0.f, 0.f, 0.f, 0.f};
+      if (d4[0] != 0.f) {
+        const float4 q = row4(i0 - C_e + c0, vimg, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += (f4(q, j) - f4(s0, j)) * d4[0];
+      }
+      if (d4[1] != 0.f) {
+        const float4 q = row4(i0 + C_e + c0, vimg, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += (f4(s0, j) - f4(q, j)) * d4[1];
+      }
+      if (d4[2] != 0.f) {
+        const float4 q = row4(i0 - W * C_e + c0, vimg, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += (f4(q, j) - f4(s0, j)) * d4[2];
+      }
+      if (d4[3] != 0.f) {
+        const float4 q = row4(i0 + W * C_e + c0, vimg, n);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] += (f4(s0, j) - f4(q, j)) * d4[3];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xs[j] += 0.5f * e[j];
     }
-    out[c] = x;
+    if (vout == 4) {
+      *reinterpret_cast<float4*>(out + c0) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+    } else if (vout == 3) {
+      *reinterpret_cast<float3*>(out + c0) = make_float3(xs[0], xs[1], xs[2]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < n) out[c0 + j] = xs[j];
+    }
   }
 }
 
