@@ -711,24 +711,52 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
       bary[2 * p + 1] = b1;
     }
     if (out) {
-      // interpolation, with the arithmetic of the interpolation kernel
+      // interpolation, with the arithmetic of the interpolation kernel, four
+      // channels a load and a store where the channel counts allow
       const int C = C_a + append_z;
       float* o = out + p * C;
+      const int vout = row_vec(C, out);
+      const bool a_al = ((vw.a_off * C_a) & 3) == 0;
+      const int va = row_vec(C_a, attr) == 3 ? 3 : row_vec(C_a, attr) == 4 && a_al ? 4 : 0;
+      float b2 = 0.f, zv = 0.f;
+      const float *a0 = attr, *a1 = attr, *a2 = attr;
       if (t >= 0) {
-        const float b2 = (1.0f - b0) - b1;
+        b2 = (1.0f - b0) - b1;
         const int32_t* row = tri_row(tri, vw, t);
         const int i0 = row[0], i1 = row[1], i2 = row[2];
-        const float* a0 = attr + (vw.a_off + i0) * C_a;
-        const float* a1 = attr + (vw.a_off + i1) * C_a;
-        const float* a2 = attr + (vw.a_off + i2) * C_a;
-        for (int c = 0; c < C_a; ++c) o[c] = (b0 * a0[c] + b1 * a1[c]) + b2 * a2[c];
+        a0 = attr + (vw.a_off + i0) * C_a;
+        a1 = attr + (vw.a_off + i1) * C_a;
+        a2 = attr + (vw.a_off + i2) * C_a;
         if (append_z) {
           const float* vb = v + vw.v_off * 3;
           const float z0 = vb[(size_t)i0 * 3 + 2], z1 = vb[(size_t)i1 * 3 + 2], z2 = vb[(size_t)i2 * 3 + 2];
-          o[C_a] = (b0 * z0 + b1 * z1) + b2 * z2;
+          zv = (b0 * z0 + b1 * z1) + b2 * z2;
         }
-      } else {
-        for (int c = 0; c < C; ++c) o[c] = 0.f;
+      }
+      for (int c0 = 0; c0 < C; c0 += 4) {
+        const int n = min(4, C - c0);
+        float xs[4] = {0.f, 0.f, 0.f, 0.f};
+        if (t >= 0) {
+          if (c0 < C_a) {
+            const int na = min(4, C_a - c0);
+            const float4 x0 = row4(a0 + c0, va, na), x1 = row4(a1 + c0, va, na), x2 = row4(a2 + c0, va, na);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              if (j < na) xs[j] = (b0 * f4(x0, j) + b1 * f4(x1, j)) + b2 * f4(x2, j);
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (append_z && c0 + j == C_a) xs[j] = zv;
+        }
+        if (vout == 4) {
+          *reinterpret_cast<float4*>(o + c0) = make_float4(xs[0], xs[1], xs[2], xs[3]);
+        } else if (vout == 3) {
+          *reinterpret_cast<float3*>(o + c0) = make_float3(xs[0], xs[1], xs[2]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (j < n) o[c0 + j] = xs[j];
+        }
       }
     }
   }
