@@ -79,7 +79,15 @@ __global__ void __launch_bounds__(256) k_interp(const mer_view* __restrict__ vie
     const float* a0 = attr + (vw.a_off + idx[0]) * C_a;
     const float* a1 = attr + (vw.a_off + idx[1]) * C_a;
     const float* a2 = attr + (vw.a_off + idx[2]) * C_a;
-    for (int c = 0; c < C_a; ++c) so[c] = (b0 * a0[c] + b1 * a1[c]) + b2 * a2[c];
+    // four channels a load where the rows allow it
+    const int va = row_vec(C_a, attr) == 3 ? 3 : row_vec(C_a, attr) == 4 && ((vw.a_off * C_a) & 3) == 0 ? 4 : 0;
+    for (int c0 = 0; c0 < C_a; c0 += 4) {
+      const int na = min(4, C_a - c0);
+      const float4 x0 = row4(a0 + c0, va, na), x1 = row4(a1 + c0, va, na), x2 = row4(a2 + c0, va, na);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j < na) so[c0 + j] = (b0 * f4(x0, j) + b1 * f4(x1, j)) + b2 * f4(x2, j);
+    }
     if (append_z) {
       const float z0 = v[(vw.v_off + idx[0]) * 3 + 2], z1 = v[(vw.v_off + idx[1]) * 3 + 2],
                   z2 = v[(vw.v_off + idx[2]) * 3 + 2];
