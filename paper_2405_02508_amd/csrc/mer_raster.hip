@@ -487,7 +487,9 @@ __global__ void __launch_bounds__(256) k_bin_big(const mer_view* __restrict__ vi
 // A record is "fast" when |A|, |B| < 2^17 (pixel offsets from the tile origin
 // fit in 31 bits) and |D| < 2^31: a covered centre's unbiased edge values lie
 // in [0, |D|], so they are the 32-bit sum of the tile-origin values' low
-// halves and the offsets, and d = |D| is the same at every pixel.
+// halves and the offsets, and d = |D| is the same at every pixel.  A fast
+// record's vertex 1/z also lie in [2^-64, 2^64], which keeps every step of
+// div_rn below a normal number.
 struct __align__(16) TileRec {
   int A[3];
   int B[3];
@@ -496,11 +498,24 @@ struct __align__(16) TileRec {
   float q[3];  // vertex 1/z
   float d;     // (float)|D|
   float qb;    // early-z bound: no key of this record exceeds it
-  unsigned tneg;  // 0xFFFFFFFF - t, low half of the visibility key
-  int t;       // triangle index in the view, -1: skip
+  unsigned tneg;  // ~t (t the triangle index in the view), low half of the visibility key; 0: skip
+  float rd;    // RN(1 / d)
   int fast;
 };
 static_assert(sizeof(TileRec) == 80, "tile record layout");
+
+// RN(a / b) from y = RN(1 / b), for a >= 0 and b >= 1 with every step a
+// normal number: q0 = RN(a y) is within 1.5 ulp of a / b, one correction
+// with the remainder (exact product in the fma) brings it within one ulp,
+// and then the remainder is exact and one more correction gives the
+// correctly rounded quotient (Markstein's theorem on division with a fused
+// multiply-add).  Five operations in place of the division's scale, fix-up
+// and reciprocal sequence; the result is the IEEE quotient bit for bit.
+__device__ __forceinline__ float div_rn(float a, float b, float y) {
+  const float q0 = a * y;
+  const float q1 = fmaf(fmaf(-b, q0, a), y, q0);
+  return fmaf(fmaf(-b, q1, a), y, q1);
+}
 
 // TRACK: keep the winner's depth-key products along the candidate loop (for
 // stored barycentrics); without it the resolve recomputes them from the
@@ -522,7 +537,7 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   __shared__ TileRec s_tr[NT];
   // single-wave tiles: the chunk's records go to s_tr nearest first
   constexpr bool kSort = NT == 64;
-  __shared__ float s_qs[kSort ? NT : 1];
+  __shared__ unsigned s_ks[kSort ? NT : 1];
   const long long g = xcd_tile(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
@@ -556,8 +571,10 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
   // when it came from this loop: the barycentrics without another gather
   float wa = 0.f, wb = 0.f, wn = 0.f;
   bool own = false;
+  const unsigned long long inside_m = __builtin_amdgcn_ballot_w64(inside);
   for (long long c0 = 0; c0 < n_items; c0 += NT) {
     const int n = (int)min((long long)NT, n_items - c0);
+    bool is_fast = false, is_slow = false;
     if (lt < n) {
       long long r;
       bool keep = true;
@@ -575,7 +592,8 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         keep = bb.x0 <= bb.x1 && bb.x1 >= x0 && bb.x0 < x0 + TW && bb.y1 >= y0 && bb.y0 < y0 + TH;
       }
       TileRec o;
-      o.t = -1;
+      o.tneg = 0u;
+      o.fast = 0;
       if (keep) {
         const Rec R = rec[r];
         long long Dabs = 0;
@@ -593,81 +611,109 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           o.q[k] = R.q[k];
         }
         o.d = (float)Dabs;
-        o.fast = (R.tl & 8) && Dabs < 2147483648ll;
+        o.rd = 1.0f / o.d;
+        const float qlo = fminf(R.q[0], fminf(R.q[1], R.q[2])), qhi = fmaxf(R.q[0], fmaxf(R.q[1], R.q[2]));
+        o.fast = (R.tl & 8) && Dabs < 2147483648ll && qlo >= 0x1p-64f && qhi <= 0x1p64f;
         // Early z: the key is a convex combination of the vertices' 1/z up to
         // a few roundings (< 2^-20 relative), so a lane whose surface is
         // already strictly nearer than every vertex skips the key (it could
         // not win, not even the tie on equal 1/z).  The test is per lane, so
-        // it holds for every tile shape.
-        o.qb = fmaxf(R.q[0], fmaxf(R.q[1], R.q[2])) * (1.0f + 0x1p-20f);
-        o.t = (int)(r - tb);
-        o.tneg = 0xFFFFFFFFu - (unsigned)o.t;
+        // it holds for every tile shape.  The bound is rounded up to the top
+        // of its group of 64 floats (still a bound, and at least the smallest
+        // normal): the sort key below keeps only the group, and the bound
+        // must not increase along the sorted order.
+        const unsigned qbits = __float_as_uint(fmaxf(qhi * (1.0f + 0x1p-20f), 0x1p-126f));
+        o.qb = __uint_as_float(qbits < 0x7F800000u ? qbits | 63u : qbits);
+        o.tneg = ~(unsigned)(r - tb);
+        is_fast = o.fast;
+        is_slow = !o.fast;
       }
-      if constexpr (kSort) s_qs[lt] = o.t >= 0 ? o.qb : -1.0f;
+      if constexpr (kSort)
+        s_ks[lt] = (is_fast ? __float_as_uint(o.qb) & ~63u : is_slow ? 64u : 0u) | (unsigned)(63 - lt);
       else s_tr[lt] = o;
       if constexpr (kSort) {
         // The winner is the largest key whatever the order, so the chunk is
-        // taken nearest first: record i goes to its rank by early-z bound qb
-        // (descending, ties by index, skipped records last).  Once no lane's
-        // surface is as far as a record's bound, no later record can win.
+        // taken nearest first: record i goes to its rank by sort key, which
+        // puts the fast records first, by early-z bound (descending), then
+        // the slow ones, then the skipped ones.  The key's low six bits hold
+        // 63 - i, so keys are distinct and the ranks a permutation.  Once no
+        // lane's surface is as far as a fast record's bound, no later fast
+        // record can win.
         __builtin_amdgcn_wave_barrier();
-        const float mq = s_qs[lt];
+        const unsigned mk = s_ks[lt];
         int rank = 0;
-        for (int i = 0; i < n; ++i) {
-          const float oq = s_qs[i];
-          rank += (oq > mq) | ((oq == mq) & (i < lt));
-        }
+        for (int i = 0; i < n; ++i) rank += s_ks[i] > mk;
         s_tr[rank] = o;
       }
     }
+    // single-wave tiles: fast records at ranks [0, n_fast), slow ones next
+    const int n_fast = kSort ? (int)__popcll(__builtin_amdgcn_ballot_w64(is_fast)) : 0;
+    const int n_slow = kSort ? (int)__popcll(__builtin_amdgcn_ballot_w64(is_slow)) : 0;
     __syncthreads();
-    for (int j = 0; j < n; ++j) {
-      const TileRec T = s_tr[j];  // five 16-byte LDS broadcasts
-      const int t = T.t;
-      if (kSort && t < 0) break;  // sorted: only skipped records follow
-      if (t < 0) continue;  // uniform across the block
+    // Fast records here; the others (rare: long edges or a large |D|) after
+    // the loop, so that this loop carries the winner through one path only.
+    // The break leaves out only fast records that cannot win (their bound
+    // is below every lane's key); the second loop tests every slow record.
+    bool slow = false;
+    for (int j = 0; j < (kSort ? n_fast : n); ++j) {
+      // the bound first, the rest of the record once it is taken (LDS
+      // broadcasts: every lane reads the same address)
+      const float qb = s_tr[j].qb, rd = s_tr[j].rd;
+      const unsigned tneg = s_tr[j].tneg;
+      if (!kSort && !tneg) continue;  // uniform across the block
       const float best_q = key_q(best);
-      if (kSort && !__ballot(inside && T.qb >= best_q)) break;  // nor can any record after it
-      if (T.fast) {
-        // 32-bit path: covered iff off_k > thr_k for all k; then the unbiased
-        // edge values are u0_k + off_k exactly (mod 2^32 and in [0, 2^31))
-        int off[3];
-        bool cov = inside & (T.qb >= best_q);
+      const unsigned long long near_m = __builtin_amdgcn_ballot_w64(qb >= best_q) & inside_m;
+      if (kSort && !near_m) break;  // nor can any fast record after it
+      if (!kSort && !s_tr[j].fast) {
+        slow = true;
+        continue;
+      }
+      const TileRec& T = s_tr[j];
+      // covered iff off_k > thr_k for all k; then the unbiased edge values
+      // are u0_k + off_k exactly (mod 2^32 and in [0, 2^31))
+      int off[3];
+      bool cov = inside & (qb >= best_q);
+      unsigned long long cov_m = near_m;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          off[k] = __mul24(T.A[k], dxs) + __mul24(T.B[k], dys);  // 24-bit signed products
-          cov &= off[k] > T.thr[k];
-        }
-        if (cov) {
-          float e[3];
+      for (int k = 0; k < 3; ++k) {
+        off[k] = __mul24(T.A[k], dxs) + __mul24(T.B[k], dys);  // 24-bit signed products
+        cov &= off[k] > T.thr[k];
+        cov_m &= __builtin_amdgcn_ballot_w64(off[k] > T.thr[k]);
+      }
+      // taken by the whole wave when any lane is covered (a wave-uniform
+      // branch): uncovered lanes compute values they never keep
+      if (cov_m) {
+        float e[3];
 #pragma unroll
-          for (int k = 0; k < 3; ++k) e[k] = (float)(int)((unsigned)T.u0[k] + (unsigned)off[k]);
-          const float a = e[0] * T.q[0];
-          const float b = e[1] * T.q[1];
-          const float c = e[2] * T.q[2];
-          float nq = a + b;
-          nq = nq + c;
-          const float qk = nq / T.d;
-          const unsigned long long k = ((unsigned long long)__float_as_uint(qk) << 32) | T.tneg;
-          if (TRACK) {
-            if (k > best) {
-              best = k;
-              wa = a;
-              wb = b;
-              wn = nq;
-              own = true;
-            }
-          } else {
-            best = k > best ? k : best;
-          }
+        for (int i = 0; i < 3; ++i) e[i] = (float)(int)((unsigned)T.u0[i] + (unsigned)off[i]);
+        const float a = e[0] * T.q[0];
+        const float b = e[1] * T.q[1];
+        const float c = e[2] * T.q[2];
+        float nq = a + b;
+        nq = nq + c;
+        const float qk = div_rn(nq, T.d, rd);  // == nq / T.d where covered
+        const unsigned long long k = ((unsigned long long)__float_as_uint(qk) << 32) | tneg;
+        const bool win = cov && k > best;
+        best = win ? k : best;
+        if (TRACK) {
+          wa = win ? a : wa;
+          wb = win ? b : wb;
+          wn = win ? nq : wn;
+          own |= win;
         }
-      } else {
+      }
+    }
+    if (kSort ? n_slow > 0 : slow) {
+      for (int j = kSort ? n_fast : 0; j < (kSort ? n_fast + n_slow : n); ++j) {
+        const TileRec T = s_tr[j];
+        if (!kSort && (!T.tneg || T.fast)) continue;
+        const int t = (int)~T.tneg;
         const Rec R = rec[tb + __builtin_amdgcn_readfirstlane(t)];
         long long E[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
           E[k] = (long long)R.A[k] * (long long)(px * 256) + (long long)R.B[k] * (long long)(py * 256) + R.C[k];
-        if (inside && covered(E) && T.qb >= best_q) {
+        if (inside && covered(E) && T.qb >= key_q(best)) {
           float e[3], d;
           edge_values(R, E, e, d);
           const float a = e[0] * R.q[0];
@@ -676,16 +722,13 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           float nq = a + b;
           nq = nq + c;
           const unsigned long long k = vis_key(nq / d, t);
+          const bool win = k > best;
+          best = win ? k : best;
           if (TRACK) {
-            if (k > best) {
-              best = k;
-              wa = a;
-              wb = b;
-              wn = nq;
-              own = true;
-            }
-          } else {
-            best = k > best ? k : best;
+            wa = win ? a : wa;
+            wb = win ? b : wb;
+            wn = win ? nq : wn;
+            own |= win;
           }
         }
       }
