@@ -521,7 +521,7 @@ __device__ __forceinline__ float div_rn(float a, float b, float y) {
 // stored barycentrics); without it the resolve recomputes them from the
 // winner's vertices when it interpolates.  bary (TRACK only) and out may be NULL.
 template <int TW, int TH, bool TRACK>
-__global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(8))) k_raster(const mer_view* __restrict__ views, int n_views,
                                                    const long long* __restrict__ tri_base,
                                                    const long long* __restrict__ tile_base,
                                                    const Rec* __restrict__ rec, const BBox* __restrict__ bbox,
@@ -535,9 +535,12 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
                                                    int C_a, int append_z, float* __restrict__ out) {
   constexpr int NT = TW * TH;
   __shared__ TileRec s_tr[NT];
-  // single-wave tiles: the chunk's records go to s_tr nearest first
+  // single-wave tiles: the chunk's records go to s_tr nearest first.  The
+  // sort keys share the first bytes of s_tr: the wave reads every key before
+  // any lane stores its record (LDS operations of one wave complete in
+  // order), and the keys are dead by then.
   constexpr bool kSort = NT == 64;
-  __shared__ unsigned s_ks[kSort ? NT : 1];
+  unsigned* const s_ks = reinterpret_cast<unsigned*>(s_tr);
   const long long g = xcd_tile(blockIdx.x, gridDim.x);
   const int lt = threadIdx.x;
   const int vi = __builtin_amdgcn_readfirstlane(find_bucket(tile_base, n_views, g));
@@ -564,12 +567,11 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
     if (count[g] != 0) atomicAdd((unsigned long long*)status + 6, 1ull);
   }
 
-  const long long p = vw.px_off + (long long)py * vw.W + px;
   // key: the small-triangle pass's result, or NULL when that pass is off
-  unsigned long long best = inside && key ? key[p - px_begin] : 0ull;
-  // products e_k q_k (k = 0, 1) and their sum over k of the current winner
-  // when it came from this loop: the barycentrics without another gather
-  float wa = 0.f, wb = 0.f, wn = 0.f;
+  unsigned long long best = inside && key ? key[vw.px_off - px_begin + (long long)py * vw.W + px] : 0ull;
+  // the current winner's barycentrics when it came from this loop, from its
+  // products e_k q_k with the resolve's arithmetic: no gather afterwards
+  float wb0 = 0.f, wb1 = 0.f;
   bool own = false;
   const unsigned long long inside_m = __builtin_amdgcn_ballot_w64(inside);
   for (long long c0 = 0; c0 < n_items; c0 += NT) {
@@ -696,9 +698,10 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
         const bool win = cov && k > best;
         best = win ? k : best;
         if (TRACK) {
-          wa = win ? a : wa;
-          wb = win ? b : wb;
-          wn = win ? nq : wn;
+          const float r = __builtin_amdgcn_rcpf(nq);
+          const float x0 = a * r, x1 = b * r;
+          wb0 = win ? x0 : wb0;
+          wb1 = win ? x1 : wb1;
           own |= win;
         }
       }
@@ -725,9 +728,10 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
           const bool win = k > best;
           best = win ? k : best;
           if (TRACK) {
-            wa = win ? a : wa;
-            wb = win ? b : wb;
-            wn = win ? nq : wn;
+            const float r = __builtin_amdgcn_rcpf(nq);
+            const float x0 = a * r, x1 = b * r;
+            wb0 = win ? x0 : wb0;
+            wb1 = win ? x1 : wb1;
             own |= win;
           }
         }
@@ -736,6 +740,11 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
     __syncthreads();
   }
   if (!inside) return;
+  // the pixel's index from the pixel coordinates again here: a 64-bit value
+  // kept across the loop would cost registers the loop needs
+  int pxr = px, pyr = py;
+  asm volatile("" : "+v"(pxr), "+v"(pyr));
+  const long long p = vw.px_off + (long long)pyr * vw.W + pxr;
   const int t = key_tri(best);
   tri_id[p] = t;
   if (depth) depth[p] = t >= 0 ? 1.0f / key_q(best) : 0.0f;
@@ -744,10 +753,16 @@ __global__ void __launch_bounds__(TW* TH) k_raster(const mer_view* __restrict__ 
     if (t >= 0) {
       // a winner not tracked here (small-triangle pass, or no tracking): the
       // same products from its vertices
-      if (!TRACK || !own) resolve_products(snap_triangle(v, vw, tri_row(tri, vw, t)), px, py, wa, wb, wn);
-      const float r = __builtin_amdgcn_rcpf(wn);
-      b0 = wa * r;
-      b1 = wb * r;
+      if (TRACK && own) {
+        b0 = wb0;
+        b1 = wb1;
+      } else {
+        float wa, wb, wn;
+        resolve_products(snap_triangle(v, vw, tri_row(tri, vw, t)), px, py, wa, wb, wn);
+        const float r = __builtin_amdgcn_rcpf(wn);
+        b0 = wa * r;
+        b1 = wb * r;
+      }
     }
     if (TRACK && bary) {
       bary[2 * p] = b0;
