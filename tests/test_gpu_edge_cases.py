@@ -96,6 +96,51 @@ def test_vertices_on_pixel_centres_and_shared_edges():
             _check(s, tile=tile, small_px=sp)
 
 
+def test_near_tied_depth_keys_match_the_oracle():
+    """Stacks of overlapping triangles whose vertex depths differ by a few
+    ulps, some exact copies and some coplanar: the winner and its depth key
+    hang on the last bit of the key's rounding, on the tile records with 32-bit
+    edge values (short edges), the 64-bit ones (edges over 512 px) and the
+    small-triangle pass."""
+    say("[edge] near-tied depth keys")
+    rng = np.random.default_rng(21)
+    H, W = 72, 80
+    z0 = np.float32(2.5)
+    vs, ts = [], []
+
+    def add(P, z):
+        n = sum(x.shape[0] for x in vs)
+        vs.append(np.concatenate([P, z[:, None]], 1).astype(np.float32))
+        ts.append(np.arange(n, n + 3, dtype=np.int32)[None])
+
+    ulp = np.float32(np.spacing(z0))
+    for i in range(48):  # short edges, random shapes over the view
+        P = rng.uniform(-6, [W + 6, H + 6], (3, 2))
+        add(P, z0 + ulp * rng.integers(-3, 4, 3).astype(np.float32))
+    for i in range(12):  # edges longer than 512 px: the 64-bit records
+        c = rng.uniform(0, [W, H])
+        P = c + rng.uniform(-2000, 2000, (3, 2))
+        add(P, z0 + ulp * rng.integers(-3, 4, 3).astype(np.float32))
+    for i in range(0, 16, 2):  # exact copies: equal keys, the smaller id wins
+        add(vs[i][:, :2], vs[i][:, 2])
+    for i in range(10):  # coplanar with the plane z = z0 + 2 ulp, other shapes
+        add(rng.uniform(-6, [W + 6, H + 6], (3, 2)), np.full(3, z0 + 2 * ulp, np.float32))
+    for i in range(60):  # small triangles near tied with the rest
+        c = rng.uniform(0, [W, H])
+        add(c + rng.uniform(-1.5, 1.5, (3, 2)), z0 + ulp * rng.integers(-3, 4, 3).astype(np.float32))
+    v, t = np.concatenate(vs), np.concatenate(ts)
+    s = _scene([(v, t, H, W)])
+    tid_ref, key_ref, _ = oracle.rasterize(v, t, H, W, with_key=True)
+    cov = tid_ref >= 0
+    assert cov.mean() > 0.9
+    for tile in [(8, 8), (16, 16)]:
+        for sp in [0, -1]:
+            got, _ = _check(s, tile=tile, small_px=sp)
+            # the depth is 1 / key, rounded once: equal to the oracle's key bit for bit
+            d = got["depth"][: H * W]
+            assert np.array_equal(d[cov].view(np.uint32), (np.float32(1) / key_ref[cov]).view(np.uint32))
+
+
 def test_backward_ignores_invalid_index_values():
     """An index image with out-of-range ids is read as background (no access
     outside the triangle table)."""
