@@ -106,11 +106,21 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
 // cycle per active lane on this chip, integer ones a few cycles per
 // instruction.  With M the tile's largest |dL/d(out)| (every contribution
 // w g has |w g| <= M, and a texel takes at most 4 x 256 of them) and
-// M < 2^e, contributions are scaled by 2^(52 - e) and rounded to integers:
-// the sums stay below 2^62, each contribution is rounded by at most
-// 2^(e - 53) <= 2^-52 M, and the sum is exact and independent of order.  A
+// M < 2^e, contributions are scaled by 2^(51 - e) and rounded to integers:
+// the sums stay below 2^61, each contribution is rounded by at most
+// 2^(e - 52) <= 2^-51 M, and the sum is exact and independent of order.  A
 // tile with a non-finite dL/d(out) adds straight to memory instead.
 constexpr int kTexWin = 3072;
+
+// round(x s) to the nearest integer (ties to even) for |x s| < 2^51, as the
+// bits of a 64-bit integer: x s + 1.5 2^52 lies in [2^52, 2^53), where the
+// binary64 spacing is 1, so the one rounding of the fused multiply-add is
+// the rounding to an integer, and the integer is the difference of the sum's
+// bits and the constant's
+__device__ __forceinline__ unsigned long long fixed_round(float x, double s) {
+  const double magic = 6755399441055744.0;  // 1.5 * 2^52
+  return (unsigned long long)(__double_as_longlong(fma((double)x, s, magic)) - __double_as_longlong(magic));
+}
 
 template <bool V4>
 __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict__ views, int n_views,
@@ -215,20 +225,45 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
   const float M = __int_as_float(s_box[4]);
   if (!any || M == 0.f) return;  // nothing to add (uniform)
   if (nwin > kTexWin || s_box[5]) {
-    if (cell.ok)
-      for (int c = 0; c < C; ++c) {
-        const float gc = g[c];
-        if (gc == 0.f) continue;
-        atomicAdd(g_tex + r00 + c, w00 * gc);
-        atomicAdd(g_tex + r10 + c, w10 * gc);
-        atomicAdd(g_tex + r01 + c, w01 * gc);
-        atomicAdd(g_tex + r11 + c, w11 * gc);
+    // Straight to memory (uniform: the whole workgroup is here).  Each wave
+    // stages its pixels' four (texel row, weight) pairs in the window's LDS,
+    // then adds them channel-fastest: lanes l and l + 1 take channels c and
+    // c + 1 of one pair, so an instruction falls on the few cache lines of
+    // 64 / C texel rows (one L2 atomic request per line) instead of on one
+    // line per lane.
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    long long* s_row = reinterpret_cast<long long*>(s_acc) + wv * 320;  // 256 texel rows (-1: none), 64 g rows
+    float* s_w = reinterpret_cast<float*>(s_acc + 4 * 320) + wv * 256;  // 256 weights
+    const long long rr[4] = {r00, r10, r01, r11};
+    const float ww[4] = {w00, w10, w01, w11};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s_row[4 * ln + k] = cell.ok ? rr[k] : -1;
+      s_w[4 * ln + k] = ww[k];
+    }
+    s_row[256 + ln] = cell.ok ? p * C : 0;
+    __syncthreads();
+    const int dq = 64 / C, dr = 64 % C;  // (pair, channel) steps per 64 values
+    int pr = ln / C, c = ln % C;
+    for (int i = ln; i < 256 * C; i += 64) {
+      const long long r = s_row[pr];
+      if (r >= 0) {
+        const float gc = g_out[s_row[256 + (pr >> 2)] + c];
+        if (gc != 0.f) atomicAdd(g_tex + r + c, s_w[pr] * gc);
       }
+      pr += dq;
+      c += dr;
+      if (c >= C) {
+        c -= C;
+        ++pr;
+      }
+    }
     return;
   }
   int e;
   frexpf(M, &e);  // M < 2^e
-  const int sh = 52 - e;
+  const int sh = 51 - e;
+  const double scale = ldexp(1.0, sh);
   for (int i = threadIdx.x; i < (int)nwin; i += blockDim.x) s_acc[i] = 0ull;
   __syncthreads();
   // channel-major window (value c of texel i at c * ncell + i): the lanes of
@@ -240,15 +275,32 @@ __global__ void __launch_bounds__(256) k_texture_bwd(const mer_view* __restrict_
     const int l10 = (int)((cell.y[0] - by0) * bw + (cell.x[1] - bx0));
     const int l01 = (int)((cell.y[1] - by0) * bw + (cell.x[0] - bx0));
     const int l11 = (int)((cell.y[1] - by0) * bw + (cell.x[1] - bx0));
-    for (int c = 0; c < C; ++c) {
-      const float gc = g[c];
-      if (gc == 0.f) continue;
+    // |w g 2^sh| < 2^51: exact in binary64, rounded to the nearest integer
+    auto add = [&](int c, float gc) {
       unsigned long long* a = s_acc + c * ncell;
-      // |w g 2^sh| < 2^52: exact in binary64, rounded to the nearest integer
-      atomicAdd(a + l00, (unsigned long long)(long long)rint(ldexp((double)(w00 * gc), sh)));
-      atomicAdd(a + l10, (unsigned long long)(long long)rint(ldexp((double)(w10 * gc), sh)));
-      atomicAdd(a + l01, (unsigned long long)(long long)rint(ldexp((double)(w01 * gc), sh)));
-      atomicAdd(a + l11, (unsigned long long)(long long)rint(ldexp((double)(w11 * gc), sh)));
+      atomicAdd(a + l00, fixed_round(w00 * gc, scale));
+      atomicAdd(a + l10, fixed_round(w10 * gc, scale));
+      atomicAdd(a + l01, fixed_round(w01 * gc, scale));
+      atomicAdd(a + l11, fixed_round(w11 * gc, scale));
+    };
+    if constexpr (V4) {
+      // the row four channels a load, every load issued before the adds
+      for (int c0 = 0; c0 < C; c0 += 8) {
+        const float4 ga = *reinterpret_cast<const float4*>(g + c0);
+        const float4 gb = c0 + 4 < C ? *reinterpret_cast<const float4*>(g + c0 + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        add(c0, ga.x);
+        add(c0 + 1, ga.y);
+        add(c0 + 2, ga.z);
+        add(c0 + 3, ga.w);
+        if (c0 + 4 < C) {
+          add(c0 + 4, gb.x);
+          add(c0 + 5, gb.y);
+          add(c0 + 6, gb.z);
+          add(c0 + 7, gb.w);
+        }
+      }
+    } else {
+      for (int c = 0; c < C; ++c) add(c, g[c]);
     }
   }
   __syncthreads();
