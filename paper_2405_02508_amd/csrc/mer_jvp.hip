@@ -63,6 +63,10 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
                                              const float* __restrict__ img, int C_e, const float* __restrict__ dv,
                                              int flags, float* __restrict__ dimg) {
   __shared__ TileTris<TS, true> T;
+  // per grid position: bit d when the pixel's triangle holds neighbour d's
+  // centre (d: 0 left, 1 right, 2 up, 3 down); a border pixel sets only the
+  // bit toward its tile neighbour
+  __shared__ unsigned char s_cm[TileDims<TS>::G * TileDims<TS>::G];
   const long long n_tiles = btile_base[n_views];
   if ((long long)blockIdx.x >= n_tiles) return;  // the grid may hold spare workgroups
   const long long tile = xcd_tile(blockIdx.x, n_tiles);
@@ -78,17 +82,36 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
 
   const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
   const int px = x0 + lx, py = y0 + ly;
-  if (px >= vw.W || py >= vw.H) return;
-  const long long p = vw.px_off + (long long)py * vw.W + px;
-  const int t = tile_rec<TS>(T, lx, ly);  // record index, -1 background
+  const int t = tile_rec<TS>(T, lx, ly);  // record index, -1 background or outside the view
   Snap S;
   S.ok = false;
   if (t >= 0) S = tile_snap(T, t);
+  const bool want_edge = dv && !(flags & MER_SKIP_EDGE);
+  if (want_edge) {
+    s_cm[tt_pos<TS>(lx, ly)] = t >= 0 ? (unsigned char)cover_mask(S, px, py) : (unsigned char)0;
+    if (threadIdx.x < 4 * TS) {  // the border, in tile_tris_build's order: top, bottom, left, right
+      const int side = threadIdx.x / TS, j = threadIdx.x % TS;
+      const int bx = side < 2 ? j : side == 2 ? -1 : TS, by = side == 0 ? -1 : side == 1 ? TS : j;
+      const int ix = side < 2 ? j : side == 2 ? 0 : TS - 1, iy = side == 0 ? 0 : side == 1 ? TS - 1 : j;
+      const int back = side == 0 ? 3 : side == 1 ? 2 : side == 2 ? 1 : 0;  // from the border pixel to the tile
+      const int tb = tile_rec<TS>(T, bx, by);
+      s_cm[tt_pos<TS>(bx, by)] =
+          tb >= 0 && contains(tile_snap(T, tb), x0 + ix, y0 + iy) ? (unsigned char)(1u << back) : (unsigned char)0;
+    }
+    __syncthreads();
+  }
+  if (px >= vw.W || py >= vw.H) return;
+  const long long p = vw.px_off + (long long)py * vw.W + px;
 
   // ---- micro-edge term: tangent of the edge position of each differing pair
   float d4[4] = {0.f, 0.f, 0.f, 0.f};  // left, right, up, down
-  if (dv && !(flags & MER_SKIP_EDGE)) {
-    unsigned pend = 0;
+  if (want_edge) {
+    // A pair of two covered pixels has a term only when one side's
+    // triangle holds the other's centre (else the triangles merely touch),
+    // and under NO_INTERSECT only when exactly one does: such pairs leave
+    // pend before any triangle is read.
+    const unsigned cm = s_cm[tt_pos<TS>(lx, ly)];
+    unsigned pend = 0, held = 0;  // held bit d: neighbour d's triangle holds this centre
     int tn4[4];
 #pragma unroll
     for (int dir = 0; dir < 4; ++dir) {
@@ -96,7 +119,11 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
       const int ny = ly + (dir == 2 ? -1 : dir == 3 ? 1 : 0);
       tn4[dir] = tile_rec<TS>(T, nx, ny);  // -1 outside the view too
       const bool inside = px + (nx - lx) >= 0 && px + (nx - lx) < vw.W && py + (ny - ly) >= 0 && py + (ny - ly) < vw.H;
-      if (inside && tn4[dir] != t) pend |= 1u << dir;
+      const unsigned cS = (s_cm[tt_pos<TS>(nx, ny)] >> (dir ^ 1)) & 1u, cN = (cm >> dir) & 1u;
+      held |= cS << dir;
+      const bool both = t >= 0 && tn4[dir] >= 0;
+      const bool term = !both || (cS | cN) && !((flags & MER_NO_INTERSECT) && (cS & cN));
+      if (inside && tn4[dir] != t && term) pend |= 1u << dir;
     }
     float drs[3] = {0.f, 0.f, 0.f};  // this pixel's own fragment tangent
     if (t >= 0 && pend) frag_tangent(T, S, t, px, py, drs);
@@ -120,9 +147,8 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
           frag_tangent(T, Sn, tn, nx, ny, drn);
           dp = drn[axis];
         } else {
-          const bool cS = contains(Sn, px, py);  // the neighbour's triangle holds this centre
-          const bool cN = contains(S, nx, ny);   // this triangle holds the neighbour's centre
-          if (!cS && !cN) continue;              // adjacent: nothing
+          const bool cS = (held >> dir) & 1u;  // the neighbour's triangle holds this centre
+          const bool cN = (cm >> dir) & 1u;    // this triangle holds the neighbour's centre
           if (cS != cN) {
             if (cS) {
               dp = drs[axis];
@@ -132,7 +158,6 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
               dp = drn[axis];
             }
           } else {
-            if (flags & MER_NO_INTERSECT) continue;
             // A = left/upper pixel.  dp = (-sA drA_axis + drA_q + sB drB_axis - drB_q) / (sB - sA)
             const float s_self = plane_slope(S, axis), s_n = plane_slope(Sn, axis);
             const float sA = selfA ? s_self : s_n, sB = selfA ? s_n : s_self;
