@@ -62,10 +62,19 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
                                                  float* __restrict__ out, long long px_begin, long long total_px) {
   const long long p = px_begin + (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int wvi = wave_view(views, n_views, p - (threadIdx.x & 63));
-  if (p >= total_px || !pixel_in_view(views, n_views, p, wvi)) return;
+  // the wave's view through scalar loads; lanes past its end (a wave across
+  // two views) look theirs up
+  const long long off0 = views[wvi].px_off, n0 = (long long)views[wvi].H * views[wvi].W;
+  bool in = p < total_px && p - off0 < n0;
+  if (__builtin_amdgcn_ballot_w64(p < total_px && p - off0 >= n0))
+    in = p < total_px && pixel_in_view(views, n_views, p, wvi);
+  if (!in) return;
   float* o = out + p * C;
-  const bool want = !tri_id || tri_id[p] >= 0;
-  const TexCell cell = tex_cell(want, want ? uv[p * ld_uv] : 0.f, want ? uv[p * ld_uv + 1] : 0.f, th, tw);
+  // the uv row (every pixel has one) and the index in flight together
+  const float u = uv[p * ld_uv], v = uv[p * ld_uv + 1];
+  const int tid = tri_id ? tri_id[p] : 0;
+  const bool want = tid >= 0;
+  const TexCell cell = tex_cell(want, u, v, th, tw);
   if (!cell.ok) {
     if constexpr (V4) {
       for (int c = 0; c < C; c += 4) *reinterpret_cast<float4*>(o + c) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -81,16 +90,23 @@ __global__ void __launch_bounds__(256) k_texture(const mer_view* __restrict__ vi
   const float* t01 = tex + ((long long)cell.y[1] * tw + cell.x[0]) * C;
   const float* t11 = tex + ((long long)cell.y[1] * tw + cell.x[1]) * C;
   if constexpr (V4) {
-    for (int c = 0; c < C; c += 4) {
-      const float4 a = *reinterpret_cast<const float4*>(t00 + c), b = *reinterpret_cast<const float4*>(t10 + c);
-      const float4 d = *reinterpret_cast<const float4*>(t01 + c), e = *reinterpret_cast<const float4*>(t11 + c);
+    auto mix = [&](float4 a, float4 b, float4 d, float4 e) {
       float4 r;
       r.x = (w00 * a.x + w10 * b.x) + (w01 * d.x + w11 * e.x);
       r.y = (w00 * a.y + w10 * b.y) + (w01 * d.y + w11 * e.y);
       r.z = (w00 * a.z + w10 * b.z) + (w01 * d.z + w11 * e.z);
       r.w = (w00 * a.w + w10 * b.w) + (w01 * d.w + w11 * e.w);
-      *reinterpret_cast<float4*>(o + c) = r;
+      return r;
+    };
+    auto ld = [](const float* q) { return *reinterpret_cast<const float4*>(q); };
+    int c = 0;
+    for (; c + 8 <= C; c += 8) {  // eight channels: all eight texel loads before the arithmetic
+      const float4 a0 = ld(t00 + c), b0 = ld(t10 + c), d0 = ld(t01 + c), e0 = ld(t11 + c);
+      const float4 a1 = ld(t00 + c + 4), b1 = ld(t10 + c + 4), d1 = ld(t01 + c + 4), e1 = ld(t11 + c + 4);
+      *reinterpret_cast<float4*>(o + c) = mix(a0, b0, d0, e0);
+      *reinterpret_cast<float4*>(o + c + 4) = mix(a1, b1, d1, e1);
     }
+    if (c < C) *reinterpret_cast<float4*>(o + c) = mix(ld(t00 + c), ld(t10 + c), ld(t01 + c), ld(t11 + c));
   } else {
     for (int c = 0; c < C; ++c) o[c] = (w00 * t00[c] + w10 * t10[c]) + (w01 * t01[c] + w11 * t11[c]);
   }
