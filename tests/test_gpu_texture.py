@@ -116,6 +116,35 @@ def test_sampler_without_index_image_and_strided_uv():
     assert np.all(out[::97] == 0) and np.all(g_uv[::97] == 0)
 
 
+@pytest.mark.parametrize("size,C", [(64, 4), (32, 3)])
+def test_nonfinite_texture_gradient_reaches_memory(size, C):
+    """dL/d(out) with +inf, -inf and NaN at a few pixels: their tiles add
+    straight to memory (the staged path), every other tile through the LDS
+    window.  The texels that become non-finite are the oracle's, and the
+    finite texels and dL/duv agree."""
+    s = small(2)
+    # uv over the whole texture across the view (no clamping at its edge)
+    uv_attr, tex = scenes.texture_inputs(s, 7, size=size, channels=C, texels_per_pixel=size / s.view(0)["W"])
+    tid, uvp = oracle_uv(s, uv_attr)
+    rng = np.random.default_rng(77)
+    g = rng.standard_normal((s.n_px, C), dtype=np.float32)
+    cov = np.flatnonzero(tid >= 0)
+    bad = rng.choice(cov, 9, replace=False)
+    g[bad[:3], 0] = np.inf
+    g[bad[3:6], C - 1] = -np.inf
+    g[bad[6:], 1] = np.nan
+    say(f"[tex] non-finite dL/d(out), texture {size}^2 x {C}")
+    _, g_tex, g_uv = run_sampler(s, tid, uvp, tex, g)
+    ref_gt, ref_gu = oracle.texture_bwd(tex, uvp, g, tid)
+    fin = np.isfinite(ref_gt)
+    assert np.isposinf(ref_gt).any() and np.isneginf(ref_gt).any() and np.isnan(ref_gt).any()
+    assert np.array_equal(np.isfinite(g_tex), fin)
+    assert np.array_equal(np.isnan(g_tex), np.isnan(ref_gt))
+    check_l2(np.where(fin, g_tex, 0), np.where(fin, ref_gt, 0), "finite g_tex")
+    ok = np.isfinite(ref_gu).all(1)
+    check_l2(g_uv[ok], ref_gu[ok], "finite g_uv")
+
+
 @pytest.mark.parametrize("k", [2, 4])
 def test_deferred_texturing_chain(k):
     """Raster -> interpolate uv -> texture on the GPU against the same chain
