@@ -657,23 +657,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
   }
   __syncthreads();
 
-  // ---- flush: one global atomic per (vertex, component) of this tile
+  // ---- flush: one global atomic per (vertex, component) of this tile,
+  // every lane on one (occupied slot, component) pair: k = i nv + j, with
+  // i = k / nv by a multiply and shift (exact for k < 2^16 / nv; here
+  // k < 256 nv <= 2816)
   const int nv = 3 + min(C_a, kCTab);
   const int nocc = s_nocc;
-  for (int i = threadIdx.x >> 4; i < nocc; i += (int)(blockDim.x >> 4)) {
+  const unsigned mdiv = (65536u + (unsigned)nv - 1u) / (unsigned)nv;
+  for (int k = threadIdx.x; k < nocc * nv; k += blockDim.x) {
+    const int i = (int)(((unsigned)k * mdiv) >> 16), j = k - i * nv;
     const int s = s_list[i];
+    const int qv = s_acc[s * kNV + j];
+    if (qv == 0) continue;
     const int key = s_key[s];
-    for (int j = threadIdx.x & 15; j < nv; j += 16) {
-      const int qv = s_acc[s * kNV + j];
-      if (qv == 0) continue;
-      int E = 0;
-      (void)frexpf(__uint_as_float(s_mx[s * 3 + (j < 3 ? 0 : j < 7 ? 1 : 2)]), &E);
-      const float x = ldexpf((float)qv, E - 22);
-      if (j < 3) {
-        if (g_v) atomicAdd(g_v + (vw.v_off + key) * 3 + j, x);
-      } else if (g_attr) {
-        atomicAdd(g_attr + (vw.a_off + key) * C_a + (j - 3), x);
-      }
+    int E = 0;
+    (void)frexpf(__uint_as_float(s_mx[s * 3 + (j < 3 ? 0 : j < 7 ? 1 : 2)]), &E);
+    const float x = ldexpf((float)qv, E - 22);
+    if (j < 3) {
+      if (g_v) atomicAdd(g_v + (vw.v_off + key) * 3 + j, x);
+    } else if (g_attr) {
+      atomicAdd(g_attr + (vw.a_off + key) * C_a + (j - 3), x);
     }
   }
   if constexpr (LOSS) {
