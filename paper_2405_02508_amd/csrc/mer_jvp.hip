@@ -31,20 +31,38 @@ __device__ __forceinline__ void screen_beta(const Snap& s, int px, int py, float
   for (int k = 0; k < 3; ++k) beta[k] = (float)E[k] * id;
 }
 
-// Tangent (x, y, 1/z) of the fragment at pixel (px, py) of the tile's
-// triangle d: the point with that centre's screen barycentrics moves with its
+// The three vertices' tangent rows (dx, dy, dz) of snapped triangle s, from
+// the view's rows dvb; read where needed rather than staged in LDS, which
+// keeps the one-wave workgroups small enough for twice the waves per CU.
+struct TriTangent {
+  float r[9];
+};
+__device__ __forceinline__ TriTangent tri_tangent(const float* __restrict__ dvb, const Snap& s) {
+  TriTangent g;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* q = dvb + (size_t)(unsigned)s.idx[k] * 3u;
+    g.r[3 * k] = q[0];
+    g.r[3 * k + 1] = q[1];
+    g.r[3 * k + 2] = q[2];
+  }
+  return g;
+}
+
+// Tangent (x, y, 1/z) of the fragment at pixel (px, py) of snapped triangle
+// s: the point with that centre's screen barycentrics moves with its
 // vertices, and 1/z_k moves by -(1/z_k)^2 dz_k.
-template <int TS>
-__device__ __forceinline__ void frag_tangent(const TileTris<TS, true>& T, const Snap& s, int d, int px, int py,
+__device__ __forceinline__ void frag_tangent(const float* __restrict__ dvb, const Snap& s, int px, int py,
                                              float dr[3]) {
+  const TriTangent g = tri_tangent(dvb, s);
   float beta[3];
   screen_beta(s, px, py, beta);
   dr[0] = dr[1] = dr[2] = 0.f;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    dr[0] += beta[k] * T.dv[3 * k][d];
-    dr[1] += beta[k] * T.dv[3 * k + 1][d];
-    dr[2] += beta[k] * ((-(s.q[k] * s.q[k])) * T.dv[3 * k + 2][d]);
+    dr[0] += beta[k] * g.r[3 * k];
+    dr[1] += beta[k] * g.r[3 * k + 1];
+    dr[2] += beta[k] * ((-(s.q[k] * s.q[k])) * g.r[3 * k + 2]);
   }
 }
 
@@ -62,7 +80,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
                                              const float* __restrict__ dattr, int C_a, int append_z,
                                              const float* __restrict__ img, int C_e, const float* __restrict__ dv,
                                              int flags, float* __restrict__ dimg) {
-  __shared__ TileTris<TS, true> T;
+  __shared__ TileTris<TS, false> T;
   // per grid position: bit d when the pixel's triangle holds neighbour d's
   // centre (d: 0 left, 1 right, 2 up, 3 down); a border pixel sets only the
   // bit toward its tile neighbour
@@ -78,7 +96,8 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
   grid_xy(local_tile, tiles_x, x0, y0);
   x0 *= TS;
   y0 *= TS;
-  tile_tris_build<TS, true>(T, vw, x0, y0, tri_id, tri, v, dv);
+  tile_tris_build<TS, false>(T, vw, x0, y0, tri_id, tri, v, nullptr);
+  const float* dvb = dv ? dv + vw.v_off * 3 : nullptr;
 
   const int lx = threadIdx.x % TS, ly = threadIdx.x / TS;
   const int px = x0 + lx, py = y0 + ly;
@@ -126,7 +145,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
       if (inside && tn4[dir] != t && term) pend |= 1u << dir;
     }
     float drs[3] = {0.f, 0.f, 0.f};  // this pixel's own fragment tangent
-    if (t >= 0 && pend) frag_tangent(T, S, t, px, py, drs);
+    if (t >= 0 && pend) frag_tangent(dvb, S, px, py, drs);
 #pragma unroll 1
     while (__ballot(pend != 0)) {
       if (pend == 0) continue;
@@ -144,7 +163,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
         const Snap Sn = tile_snap(T, tn);
         if (t < 0) {
           float drn[3];
-          frag_tangent(T, Sn, tn, nx, ny, drn);
+          frag_tangent(dvb, Sn, nx, ny, drn);
           dp = drn[axis];
         } else {
           const bool cS = (held >> dir) & 1u;  // the neighbour's triangle holds this centre
@@ -154,7 +173,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
               dp = drs[axis];
             } else {
               float drn[3];
-              frag_tangent(T, Sn, tn, nx, ny, drn);
+              frag_tangent(dvb, Sn, nx, ny, drn);
               dp = drn[axis];
             }
           } else {
@@ -164,7 +183,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
             const float dlt = sB - sA;
             if (!(dlt > 0.f) || !isfinite(dlt)) continue;
             float drn[3];
-            frag_tangent(T, Sn, tn, nx, ny, drn);
+            frag_tangent(dvb, Sn, nx, ny, drn);
             const float* drA = selfA ? drs : drn;
             const float* drB = selfA ? drn : drs;
             const float num = ((-sA) * drA[axis] + drA[2]) + (sB * drB[axis] - drB[2]);
@@ -190,11 +209,12 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
     if (dv) {
       // the material point at this centre moves by delta = sum_j beta_j dv_j,
       // so beta_i changes by -grad_P beta_i . delta
+      const TriTangent gt = tri_tangent(dvb, S);
       float ex = 0.f, ey = 0.f;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        ex += pb.beta[j] * T.dv[3 * j][t];
-        ey += pb.beta[j] * T.dv[3 * j + 1][t];
+        ex += pb.beta[j] * gt.r[3 * j];
+        ey += pb.beta[j] * gt.r[3 * j + 1];
       }
       const float invD = 256.0f * __builtin_amdgcn_rcpf(S.D < 0 ? -pb.d : pb.d);  // (float)D, already converted
       float dw[3];
@@ -204,7 +224,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
         const float gxi = (float)(-(S.Y[c] - S.Y[a])) * invD;
         const float gyi = (float)(S.X[c] - S.X[a]) * invD;
         const float dbeta = -(gxi * ex + gyi * ey);
-        dw[i] = dbeta * S.q[i] + pb.beta[i] * ((-(S.q[i] * S.q[i])) * T.dv[3 * i + 2][t]);
+        dw[i] = dbeta * S.q[i] + pb.beta[i] * ((-(S.q[i] * S.q[i])) * gt.r[3 * i + 2]);
       }
       const float dW = (dw[0] + dw[1]) + dw[2];
       const float iW = __builtin_amdgcn_rcpf(pb.Wq);
@@ -212,7 +232,7 @@ __global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ vi
       for (int k = 0; k < 3; ++k) db[k] = (dw[k] - b[k] * dW) * iW;
       if (append_z) {
         zt = (db[0] * S.z[0] + db[1] * S.z[1]) + db[2] * S.z[2];
-        zt += (b[0] * T.dv[2][t] + b[1] * T.dv[5][t]) + b[2] * T.dv[8][t];
+        zt += (b[0] * gt.r[2] + b[1] * gt.r[5]) + b[2] * gt.r[8];
       }
     }
   }
