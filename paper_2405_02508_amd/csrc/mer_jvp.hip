@@ -72,8 +72,11 @@ __device__ __forceinline__ void frag_tangent(const float* __restrict__ dvb, cons
 // differs, the pair's edge tangent dp (d_dir); then per channel
 //   dimg = interior tangent (c < C_out) + 1/2 sum_dir (I_A - I_B) d_dir
 // with A the left/upper pixel of each pair.
+// Six waves per SIMD (80 registers, a few bytes of spills) rather than the
+// five the unbounded allocation allows: the kernel waits on dependent loads
+// more than it issues.
 template <int TS>
-__global__ void __launch_bounds__(TS * TS) k_jvp(const mer_view* __restrict__ views, int n_views,
+__global__ void __launch_bounds__(TS * TS) __attribute__((amdgpu_waves_per_eu(6))) k_jvp(const mer_view* __restrict__ views, int n_views,
                                              const long long* __restrict__ btile_base,
                                              const float* __restrict__ v, const int32_t* __restrict__ tri,
                                              const int32_t* __restrict__ tri_id, const float* __restrict__ attr,
