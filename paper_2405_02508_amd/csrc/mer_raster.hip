@@ -517,9 +517,10 @@ __device__ __forceinline__ float div_rn(float a, float b, float y) {
   return fmaf(fmaf(-b, q1, a), y, q1);
 }
 
-// TRACK: keep the winner's depth-key products along the candidate loop (for
-// stored barycentrics); without it the resolve recomputes them from the
-// winner's vertices when it interpolates.  bary (TRACK only) and out may be NULL.
+// TRACK: keep the winner's barycentrics along the candidate loop, formed
+// from its depth-key products with the resolve's own arithmetic (for stored
+// barycentrics); without it the resolve recomputes them from the winner's
+// vertices when it interpolates.  bary (TRACK only) and out may be NULL.
 template <int TW, int TH, bool TRACK>
 __global__ void __launch_bounds__(TW* TH) __attribute__((amdgpu_waves_per_eu(8))) k_raster(const mer_view* __restrict__ views, int n_views,
                                                    const long long* __restrict__ tri_base,
